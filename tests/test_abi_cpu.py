@@ -1,0 +1,113 @@
+"""The C-ABI library loads, exports every function include/sdtw.h declares,
+and rejects invalid arguments on the host before any HIP call (so these run
+without a GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdtw.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2403_06931_amd import _lib
+    return _lib
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdtw_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(L.lib, n), n
+    # and the shared object really exports them (not just resolvable by ctypes)
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_status_strings(L):
+    for s in (0, -1, -2, -3, -4, 7):
+        assert isinstance(L.status_string(s), str) and L.status_string(s)
+
+
+def test_variants_describe(L):
+    import paper_2403_06931_amd as P
+    n = P.sdtw_variant_count()
+    assert n >= 1
+    for v in range(n):
+        r, t, w = P.sdtw_variant_info(v)
+        assert r >= 1 and t in (4, 8, 16) and 1 <= w <= 16
+        assert 16 % t == 0   # checkpoint intervals are multiples of 16
+    with pytest.raises(P.SdtwError):
+        P.sdtw_variant_info(n)
+
+
+def _vp(x):
+    return ctypes.c_void_p(x)
+
+
+FAKE = 0x100000   # never dereferenced: validation fails first
+
+
+def _fwd(L, lens, batch=None, ref_len=100, kind=0, flags=0, ws_bytes=1 << 40, q=FAKE, r=FAKE,
+         c=FAKE, e=FAKE, ws=FAKE, ckpt=0, every=0, variant=-1, dlens=FAKE):
+    h = np.ascontiguousarray(lens, dtype=np.int32)
+    b = h.size if batch is None else batch
+    return L.lib.sdtw_forward(_vp(q), _vp(h.ctypes.data if h.size else 0), _vp(dlens), b,
+                              _vp(r), ref_len, kind, _vp(c), _vp(e), _vp(ckpt), every,
+                              variant, flags, _vp(ws), ws_bytes, _vp(0))
+
+
+def test_forward_rejects_invalid_arguments(L):
+    E = L.SDTW_ERR_INVALID_ARG
+    assert _fwd(L, [3, 4], q=0) == E
+    assert _fwd(L, [3, 4], r=0) == E
+    assert _fwd(L, [3, 4], c=0) == E
+    assert _fwd(L, [3, 4], e=0) == E
+    assert _fwd(L, [3, 4], ws=0) == E
+    assert _fwd(L, [3, 4], dlens=0) == E
+    assert _fwd(L, [3, 0]) == E                  # empty query
+    assert _fwd(L, [3, -2]) == E
+    assert _fwd(L, [3, 4], batch=0) == E
+    assert _fwd(L, [3, 4], ref_len=0) == E
+    assert _fwd(L, [3, 4], ref_len=(1 << 30) + 1) == E
+    assert _fwd(L, [3, 4], kind=2) == E
+    assert _fwd(L, [3, 4], flags=64) == E
+    assert _fwd(L, [3, 4], ws=FAKE + 4) == E     # misaligned workspace
+    # checkpointing: interval must be a positive multiple of 16 and the buffer present
+    assert _fwd(L, [3, 4], flags=L.SDTW_F_CHECKPOINT, every=0, ckpt=FAKE) == E
+    assert _fwd(L, [3, 4], flags=L.SDTW_F_CHECKPOINT, every=24, ckpt=FAKE) == E
+    assert _fwd(L, [3, 4], flags=L.SDTW_F_CHECKPOINT, every=32, ckpt=0) == E
+    assert _fwd(L, [3, 4], variant=10**6) == L.SDTW_ERR_UNSUPPORTED
+    assert _fwd(L, [3, 4], ws_bytes=16) == L.SDTW_ERR_WORKSPACE
+
+
+def test_workspace_sizes(L):
+    import paper_2403_06931_amd as P
+    lens = np.array([5, 7, 300], np.int32)
+    a = P.sdtw_forward_workspace_bytes(lens, 1000)
+    b = P.sdtw_forward_workspace_bytes(lens, 100000)
+    assert 0 < a < b
+    assert b >= 3 * 100000 * 4            # one last-row buffer per query
+    assert P.sdtw_forward_workspace_bytes(np.array([0], np.int32), 10) == 0
+    assert P.sdtw_forward_workspace_bytes(lens, 0) == 0
+    pers = P.sdtw_forward_workspace_bytes(np.full(10000, 300, np.int32), 1000,
+                                          P.SDTW_F_PERSISTENT)
+    assert pers < P.sdtw_forward_workspace_bytes(np.full(10000, 300, np.int32), 1000)
+    # checkpoint columns: ceil(M/K) - 1 per query row
+    assert P.sdtw_checkpoint_floats(lens, 1000, 256) == lens.sum() * 3
+    assert P.sdtw_checkpoint_floats(lens, 1024, 256) == lens.sum() * 3
+    assert P.sdtw_checkpoint_floats(lens, 1025, 256) == lens.sum() * 4
+    assert P.sdtw_checkpoint_floats(lens, 256, 256) == 0
