@@ -156,6 +156,53 @@ def batched_leg(P, torch, steps, warmup):
             "bit_identical_to_bucketed": bool(same)}
 
 
+def fwd_bwd_leg(P, torch, steps, warmup):
+    import numpy as np
+
+    import workloads
+    w = workloads.make_config(4)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    K = 1024
+    flags = P.SDTW_F_CHECKPOINT
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags), dev)
+    wsb = P.workspace(P.sdtw_backward_workspace_bytes(w.lens, w.ref_len, K), dev)
+    ckpt = torch.empty(P.sdtw_checkpoint_floats(w.lens, w.ref_len, K), dtype=torch.float32,
+                       device=dev)
+    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    g = torch.ones(w.batch, dtype=torch.float32, device=dev)
+    gq = torch.empty_like(q)
+    gr = torch.empty_like(r)
+
+    def fwd():
+        P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, ckpt=ckpt, ckpt_every=K,
+                       flags=flags, workspace_buf=ws)
+
+    def bwd():
+        P.sdtw_backward(q, w.lens, l, r, 0, g, end, ckpt, K, grad_queries=gq,
+                        grad_reference=gr, workspace_buf=wsb)
+
+    def both():
+        fwd()
+        bwd()
+    _, f_ms = time_steps(fwd, steps, warmup, torch)
+    _, b_ms = time_steps(bwd, steps, warmup, torch)
+    _, fb_ms = time_steps(both, steps, warmup, torch)
+    plain_var = P.sdtw_default_variant(w.lens, w.ref_len, 0)
+
+    def plain():
+        P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, workspace_buf=ws)
+    _, p_ms = time_steps(plain, steps, warmup, torch)
+    return {"workload": w.name, "cells": w.cells, "ckpt_every": K,
+            "gcups": w.cells / (fb_ms * 1e6), "ms_per_step": fb_ms,
+            "fwd_ckpt_ms": f_ms, "bwd_ms": b_ms, "plain_fwd_ms": p_ms,
+            "plain_fwd_gcups": w.cells / (p_ms * 1e6),
+            "variant": P.sdtw_variant_info(plain_var)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,7 +279,7 @@ def main():
         del ws
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(P, torch, steps=3, warmup=1)
-        out["fwd_bwd"] = None
+        out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1)
     print(json.dumps(out), flush=True)
 
 

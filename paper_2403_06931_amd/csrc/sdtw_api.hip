@@ -163,6 +163,45 @@ int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t 
   return best;
 }
 
+// Backward: wavefronts per query from the longest query (directions for
+// 64*W lanes x rows must fit the 128 KiB LDS buffer); 0 = unsupported.
+int bwd_waves(int32_t nmax) {
+  if (nmax <= sdtw::BwdShape<4>::MAX_ROWS) return 4;
+  if (nmax <= sdtw::BwdShape<2>::MAX_ROWS) return 2;
+  if (nmax <= sdtw::BwdShape<1>::MAX_ROWS) return 1;
+  return 0;
+}
+
+const void* bwd_kernel(int w, int kind) {
+  if (w == 4) return kind == 0 ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<4, 0>)
+                               : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<4, 1>);
+  if (w == 2) return kind == 0 ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<2, 0>)
+                               : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<2, 1>);
+  return kind == 0 ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<1, 0>)
+                   : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<1, 1>);
+}
+
+struct BwdLayout {
+  size_t offsets, part, lo, colbuf, total;
+};
+
+BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t ckpt_every,
+                     int w) {
+  BwdLayout L{};
+  size_t at = 0;
+  L.offsets = at;
+  at = align_up(at + sizeof(int64_t) * ((size_t)batch + 1), kAlign);
+  L.lo = at;
+  at = align_up(at + sizeof(int32_t) * (size_t)batch, kAlign);
+  L.part = at;
+  at = align_up(at + sizeof(float) * (size_t)batch * (size_t)row_stride_floats(ref_len), kAlign);
+  L.colbuf = at;
+  const int64_t seg_per_block = (ckpt_every + 256 * w - 1) / (256 * w);
+  at = align_up(at + sizeof(float) * (size_t)total_len * (size_t)seg_per_block, kAlign);
+  L.total = at;
+  return L;
+}
+
 int launch(const void* fn, dim3 grid, dim3 block, void** args, hipStream_t stream) {
   hipError_t e = hipLaunchKernel(fn, grid, block, args, 0, stream);
   return e == hipSuccess ? SDTW_OK : SDTW_ERR_HIP;
@@ -299,19 +338,84 @@ int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_
 
 size_t sdtw_backward_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
                                      int32_t ckpt_every) {
-  (void)h_query_lens; (void)batch; (void)ref_len; (void)ckpt_every;
-  return 0;
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len) || ckpt_every < 1)
+    return 0;
+  const int w = bwd_waves(nmax);
+  if (w == 0) return 0;
+  return bwd_layout(batch, total, ref_len, ckpt_every, w).total;
 }
 
 int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
                   int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
                   const float* grad_cost, const int64_t* end_pos, const float* ckpt,
                   int32_t ckpt_every, float* grad_queries, float* grad_reference, void* workspace,
-                  size_t workspace_bytes, void* stream) {
-  (void)queries; (void)h_query_lens; (void)query_lens; (void)batch; (void)reference;
-  (void)ref_len; (void)cost_kind; (void)grad_cost; (void)end_pos; (void)ckpt; (void)ckpt_every;
-  (void)grad_queries; (void)grad_reference; (void)workspace; (void)workspace_bytes; (void)stream;
-  return SDTW_ERR_UNSUPPORTED;
+                  size_t workspace_bytes, void* stream_ptr) {
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!queries || !query_lens || !reference || !grad_cost || !end_pos || !grad_queries ||
+      !grad_reference || !workspace)
+    return SDTW_ERR_INVALID_ARG;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
+    return SDTW_ERR_INVALID_ARG;
+  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
+    return SDTW_ERR_INVALID_ARG;
+  if (ckpt_every < 1 || ckpt_every % kCkptQuantum != 0) return SDTW_ERR_INVALID_ARG;
+  const int64_t nck = n_ckpt_of(ref_len, ckpt_every);
+  if (nck > 0 && ckpt == nullptr) return SDTW_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  const int w = bwd_waves(nmax);
+  if (w == 0) return SDTW_ERR_UNSUPPORTED;
+  const BwdLayout L = bwd_layout(batch, total, ref_len, ckpt_every, w);
+  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+  char* ws = static_cast<char*>(workspace);
+  sdtw::BwdParams p{};
+  p.queries = queries;
+  p.lens = query_lens;
+  p.offsets = nullptr;
+  p.reference = reference;
+  p.grad_cost = grad_cost;
+  p.end_pos = end_pos;
+  p.ckpt = ckpt;
+  p.grad_q = grad_queries;
+  p.ref_part = reinterpret_cast<float*>(ws + L.part);
+  p.path_lo = reinterpret_cast<int32_t*>(ws + L.lo);
+  p.colbuf = reinterpret_cast<float*>(ws + L.colbuf);
+  p.part_stride = row_stride_floats(ref_len);
+  p.batch = batch;
+  p.ref_len = (int32_t)ref_len;
+  p.ckpt_every = ckpt_every;
+  p.n_ckpt = (int32_t)nck;
+  p.seg_per_block = (ckpt_every + 256 * w - 1) / (256 * w);
+
+  if (batch > kInKernelOffsetBatch) {
+    int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
+                    dim3(sdtw::kScanThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+    p.offsets = offs;
+  }
+  {
+    const void* fn = bwd_kernel(w, cost_kind);
+    void* args[] = {(void*)&p};
+    int rc = launch(fn, dim3(batch), dim3(64 * w), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  {
+    const float* part = p.ref_part;
+    int64_t stride = p.part_stride;
+    const int32_t* lo = p.path_lo;
+    int32_t m = p.ref_len;
+    void* args[] = {(void*)&part, (void*)&stride, (void*)&lo, (void*)&end_pos, (void*)&batch,
+                    (void*)&m, (void*)&grad_reference};
+    const int grid = (int)((ref_len + sdtw::kRefReduceThreads - 1) / sdtw::kRefReduceThreads);
+    return launch(reinterpret_cast<const void*>(&sdtw::sdtw_ref_reduce_kernel), dim3(grid),
+                  dim3(sdtw::kRefReduceThreads), args, stream);
+  }
 }
 
 }  // extern "C"

@@ -111,3 +111,35 @@ def test_workspace_sizes(L):
     assert P.sdtw_checkpoint_floats(lens, 1024, 256) == lens.sum() * 3
     assert P.sdtw_checkpoint_floats(lens, 1025, 256) == lens.sum() * 4
     assert P.sdtw_checkpoint_floats(lens, 256, 256) == 0
+
+
+def _bwd(L, lens, ref_len=100, kind=0, every=64, ckpt=FAKE, ws_bytes=1 << 40, **ptrs):
+    h = np.ascontiguousarray(lens, dtype=np.int32)
+    a = dict(q=FAKE, dlens=FAKE, r=FAKE, g=FAKE, e=FAKE, gq=FAKE, gr=FAKE, ws=FAKE)
+    a.update(ptrs)
+    return L.lib.sdtw_backward(_vp(a["q"]), _vp(h.ctypes.data), _vp(a["dlens"]), h.size,
+                               _vp(a["r"]), ref_len, kind, _vp(a["g"]), _vp(a["e"]),
+                               _vp(ckpt), every, _vp(a["gq"]), _vp(a["gr"]), _vp(a["ws"]),
+                               ws_bytes, _vp(0))
+
+
+def test_backward_rejects_invalid_arguments(L):
+    E = L.SDTW_ERR_INVALID_ARG
+    for name in ("q", "dlens", "r", "g", "e", "gq", "gr", "ws"):
+        assert _bwd(L, [3, 4], **{name: 0}) == E, name
+    assert _bwd(L, [3, 0]) == E
+    assert _bwd(L, [3, 4], kind=5) == E
+    assert _bwd(L, [3, 4], every=0) == E
+    assert _bwd(L, [3, 4], every=24) == E
+    assert _bwd(L, [3, 4], ref_len=1000, every=64, ckpt=0) == E   # checkpoints needed
+    assert _bwd(L, [3, 4], ws_bytes=8) == L.SDTW_ERR_WORKSPACE
+    assert _bwd(L, [5000], ref_len=100) == L.SDTW_ERR_UNSUPPORTED   # longer than 2,048 rows
+    assert _bwd(L, [3, 4], ws=FAKE + 8) == E
+
+
+def test_backward_workspace_sizes(L):
+    import paper_2403_06931_amd as P
+    lens = np.array([100, 1000, 2048], np.int32)
+    assert P.sdtw_backward_workspace_bytes(lens, 50000, 1024) >= 3 * 50000 * 4
+    assert P.sdtw_backward_workspace_bytes(np.array([2049], np.int32), 100, 64) == 0
+    assert P.sdtw_backward_workspace_bytes(lens, 50000, 0) == 0
