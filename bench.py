@@ -9,8 +9,10 @@ call over the whole batch (DP fill, last-row minimum and end position), with
 every input already resident in device memory.
 
 Prints ONE JSON line.  Beside the headline value it reports:
-  roofline      the dominant kernel against the FP32 VALU roofline
-                (256 CUs x 64 lanes x 2.4 GHz / 4 VALU ops per DP cell);
+  roofline      the dominant kernel against the FP32 VALU roofline: gfx950
+                issues up to two VGPR-operand FP32 VALU instructions per SIMD
+                per quad-cycle, i.e. 256 CUs x 128 lanes x 2.4 GHz, divided by
+                the 4 VALU instructions of a DP cell;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   batched       the persistent uneven-length form (4,096 queries of
                 250..4,000 samples vs 200,000) and the same batch run as a
@@ -34,11 +36,11 @@ PAPER_CELLS = 512 * 2000 * 100000
 PAPER_GCUPS = PAPER_CELLS / (PAPER_MS * 1e6)
 PEAK_CUS = 256
 PEAK_GHZ = 2.4
-LANES = 64
+LANES_PER_CU_CLK = 128      # 4 SIMDs x 16 lanes x 2 (VALU dual issue)
 
 
-def valu_peak_gcups(ops_per_cell, cus=PEAK_CUS, ghz=PEAK_GHZ):
-    return cus * LANES * ghz / ops_per_cell   # G lane-instr/s / instr per cell
+def valu_peak_gcups(ops_per_cell, cus=PEAK_CUS, ghz=PEAK_GHZ, lanes=LANES_PER_CU_CLK):
+    return cus * lanes * ghz / ops_per_cell   # G lane-instr/s / instr per cell
 
 
 def source_digest():
@@ -70,6 +72,20 @@ def measured_traffic(kernel_tag):
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def valu_issue_probe():
+    """Build (into _build/) and run bench_valu_issue.hip; return its records."""
+    import subprocess
+    src = os.path.join(ROOT, "bench_valu_issue.hip")
+    exe = os.path.join(ROOT, "_build", "bench_valu_issue")
+    if not os.path.exists(exe) or os.path.getmtime(exe) < os.path.getmtime(src):
+        os.makedirs(os.path.dirname(exe), exist_ok=True)
+        subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-ffp-contract=off",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src, "-o", exe],
+                       check=True, capture_output=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    return [json.loads(line) for line in out.splitlines() if line.startswith("{")]
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -120,7 +136,11 @@ def batched_leg(P, torch, steps, warmup):
     ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags), dev)
     cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
     end = torch.empty(w.batch, dtype=torch.int64, device=dev)
-    variant = P.sdtw_default_variant(w.lens, w.ref_len, flags)
+    rec = {}
+    # persistent candidates: at most four wavefronts per query (wider teams
+    # waste most of their lanes on the short queries of this batch)
+    cands = [v for v in range(P.sdtw_variant_count()) if P.sdtw_variant_info(v)[2] <= 4]
+    variant = P.autotune.tune(q, w.lens, l, r, 0, flags, candidates=cands, reps=1, record=rec)
 
     def persistent():
         P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, flags=flags, variant=variant,
@@ -151,6 +171,7 @@ def batched_leg(P, torch, steps, warmup):
                for idx, _, _, _, _, cb, _ in buckets)
     del ws
     return {"workload": w.name, "cells": w.cells, "variant": P.sdtw_variant_info(variant),
+            "tuned_over": len(rec.get("times_ms", {})),
             "gcups": w.cells / (ev_ms * 1e6), "ms_per_step": ev_ms,
             "bucketed_loop_gcups": w.cells / (bev * 1e6), "bucketed_loop_ms": bev,
             "bit_identical_to_bucketed": bool(same)}
@@ -211,6 +232,10 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
+    ap.add_argument("--valu-issue-probe", action="store_true",
+                    help="only measure the FP32 VALU issue rate (bench_valu_issue.hip) and exit")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the library's built-in variant choice instead of timing all variants")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -218,6 +243,11 @@ def main():
                                    "over queries without communication, so run --gpus 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    if args.valu_issue_probe:
+        for rec in valu_issue_probe():
+            print(json.dumps(rec), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -234,7 +264,12 @@ def main():
     ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
     cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
     end = torch.empty(w.batch, dtype=torch.int64, device=dev)
-    variant = args.variant if args.variant >= 0 else P.sdtw_default_variant(w.lens, w.ref_len, 0)
+    if args.variant >= 0:
+        variant = args.variant
+    elif args.no_tune:
+        variant = P.sdtw_default_variant(w.lens, w.ref_len, 0)
+    else:
+        variant = P.autotune.tune(q, w.lens, l, r, 0, 0, reps=3)
 
     def step():
         P.sdtw_forward(q, w.lens, l, r, P.SDTW_COST_SQUARED, cost=cost, end_pos=end,
@@ -245,7 +280,7 @@ def main():
     value = cells / (wall_ms * 1e6)
     achieved = cells / (ev_ms * 1e6)          # one kernel launch per step at this batch size
     peak = valu_peak_gcups(4)
-    R, T, W = P.sdtw_variant_info(variant)
+    R, T, W, KS = P.sdtw_variant_info(variant)
     gc = cost.cpu().numpy()
     ge = end.cpu().numpy()
     kernel_tag = "sdtw_fwd_512x2000_vs_100k"
@@ -264,13 +299,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "queries": w.batch, "query_len": 2000,
                    "ref_len": w.ref_len, "cost": "squared", "cells": cells,
-                   "variant": {"rows_per_lane": R, "tile_cols": T, "waves": W},
+                   "variant": {"rows_per_lane": R, "tile_cols": T, "waves": W,
+                               "steps_per_barrier": KS},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "GCUPS",
                      "frac": achieved / peak, "traffic": measured_traffic(kernel_tag),
-                     "kernel": f"sdtw_fwd_kernel<{R},{T},{W},squared>",
+                     "kernel": f"sdtw_fwd_kernel<{R},{T},{W},{KS},squared>",
                      "kernel_ms": ev_ms,
-                     "peak_basis": "256 CU x 64 lanes x 2.4 GHz / 4 VALU ops per cell",
+                     "peak_basis": "256 CU x 128 lanes/clk (VALU dual issue) x 2.4 GHz / "
+                                   "4 VALU ops per cell",
+                     "single_issue_peak": valu_peak_gcups(4, lanes=64),
                      "device_cus": props.multi_processor_count},
     }
     if not args.no_cpu_baseline:

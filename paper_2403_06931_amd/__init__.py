@@ -12,3 +12,4 @@ from .api import (SDTW_COST_ABSOLUTE, SDTW_COST_SQUARED, SDTW_F_CHECKPOINT,  # n
                   sdtw_forward_workspace_bytes, sdtw_variant_count, sdtw_variant_info, workspace)
 from .graph import ForwardGraph  # noqa: F401,E402
 from .autograd import SDTWFunction, sdtw  # noqa: F401,E402
+from . import autotune  # noqa: F401,E402

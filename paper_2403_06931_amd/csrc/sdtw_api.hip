@@ -11,6 +11,11 @@
 #include "sdtw_argmin.hpp"
 #include "sdtw_bwd.hpp"
 #include "sdtw_fwd.hpp"
+#include "sdtw_setup.hpp"
+#include "sdtw_variant.hpp"
+
+#include "sdtw_variants.inc"
+SDTW_VARIANTS(SDTW_DECLARE_VARIANT)
 
 namespace {
 
@@ -21,36 +26,20 @@ constexpr int kCkptQuantum = 16;   // ckpt_every must be a multiple of every til
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
-struct Variant {
-  int R, T, W;
-  // [kind][checkpoint]
-  const void* plain[2][2];
-  const void* persistent[2][2];
-  int lds_bytes;
-};
+using sdtw::Variant;
 
-template <int R, int T, int W>
-Variant make_variant() {
-  Variant v;
-  v.R = R;
-  v.T = T;
-  v.W = W;
-  v.plain[0][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 0, false>);
-  v.plain[0][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 0, true>);
-  v.plain[1][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 1, false>);
-  v.plain[1][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_kernel<R, T, W, 1, true>);
-  v.persistent[0][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 0, false>);
-  v.persistent[0][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 0, true>);
-  v.persistent[1][0] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 1, false>);
-  v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw::sdtw_fwd_persistent_kernel<R, T, W, 1, true>);
-  v.lds_bytes = (int)(sizeof(float) * sdtw::FwdShape<R, T, W>::LDS_FLOATS);
-  return v;
+const Variant& variant(int i) {
+#define SDTW_VARIANT_ENTRY(i, R, T, W, KS) sdtw_variant_entry_##i(),
+  static const Variant table[] = {SDTW_VARIANTS(SDTW_VARIANT_ENTRY)};
+#undef SDTW_VARIANT_ENTRY
+  return table[i];
 }
 
-const Variant& variant(int i);
-int variant_count();
-
-#include "sdtw_variants.inc"
+int variant_count() {
+#define SDTW_COUNT_ONE(i, R, T, W, KS) +1
+  return 0 SDTW_VARIANTS(SDTW_COUNT_ONE);
+#undef SDTW_COUNT_ONE
+}
 
 // ------------------------------------------------------------------ checks
 
@@ -110,23 +99,28 @@ int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
 }
 
 // Estimated relative time of a variant on this batch (used when the caller
-// lets the library choose): padded cells over the usable parallelism.
+// lets the library choose): padded cells x VALU instructions per cell over
+// the issue rate the launch can sustain.  gfx950 dual-issues VALU from two
+// ready wavefronts of a SIMD, so the rate grows with resident wavefronts per
+// SIMD (factors measured on 512 x 2,000 vs 100,000 and 256 x 1,000 vs 50,000).
 double variant_cost(const Variant& v, const int32_t* h_lens, int32_t batch, int64_t ref_len,
                     int cus) {
   const int64_t rows = 64LL * v.R * v.W;
   const int64_t ntiles = (ref_len + v.T - 1) / v.T;
-  const int64_t skew = 64LL * v.W - 1 + (v.W - 1) * (sdtw::kStepsPerBarrier - 1);
+  const int64_t skew = 64LL * v.W - 1 + (v.W - 1) * (v.KS - 1);
   double cells = 0;
   for (int32_t b = 0; b < batch; ++b) {
     const int64_t passes = (h_lens[b] + rows - 1) / rows;
     cells += (double)passes * rows * (double)(ntiles + skew) * v.T;
   }
-  // per-cell VALU work: 4 cell ops plus one DPP move per row block column
-  const double per_cell = 4.0 + 1.0 / v.R + 6.0 / (v.R * v.T);
-  // waves wanted: two per SIMD (4 SIMDs per CU)
-  const double waves = (double)batch * v.W;
-  const double fill = std::min(1.0, waves / (2.0 * 4.0 * cus));
-  return cells * per_cell / fill;
+  // per-cell VALU work: 4 cell ops, one DPP move per row-block column, and
+  // about 8 per-step instructions
+  const double per_cell = 4.0 + 1.0 / v.R + 8.0 / (v.R * v.T);
+  const double wps = (double)batch * v.W / (4.0 * cus);          // wavefronts per SIMD
+  static const double kIssue[] = {0.0, 0.55, 0.75, 0.85, 1.0};   // by min(4, ceil(wps))
+  const int slot = wps <= 0 ? 1 : (wps >= 4 ? 4 : (int)(wps + 0.999));
+  const double rate = kIssue[slot] * std::min(1.0, wps / slot);
+  return cells * per_cell / rate;
 }
 
 // Compute units of the current device (read once per device; a CPX or other
@@ -226,12 +220,14 @@ const char* sdtw_status_string(int status) {
 
 int32_t sdtw_variant_count(void) { return variant_count(); }
 
-int sdtw_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* tile_cols, int32_t* waves) {
+int sdtw_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* tile_cols, int32_t* waves,
+                      int32_t* steps_per_barrier) {
   if (v < 0 || v >= variant_count()) return SDTW_ERR_UNSUPPORTED;
   const Variant& x = variant(v);
   if (rows_per_lane) *rows_per_lane = x.R;
   if (tile_cols) *tile_cols = x.T;
   if (waves) *waves = x.W;
+  if (steps_per_barrier) *steps_per_barrier = x.KS;
   return SDTW_OK;
 }
 

@@ -58,25 +58,31 @@ struct FwdParams {
 
 constexpr int kStepsPerBarrier = 8;
 
-template <int R, int T, int W>
+template <int R, int T, int W, int KS = kStepsPerBarrier>
 struct FwdShape {
-  static constexpr int KSTEP = kStepsPerBarrier;
-  static constexpr int LAG = KSTEP - 1;
-  static constexpr int SH = 2 * KSTEP;                        // handoff ring, tiles
-  static constexpr int SPAN = kWave * W + (W - 1) * LAG + 2 * KSTEP + 2;
+  static_assert(KS % 2 == 0, "the step loop is unrolled by two");
+  static constexpr int KSTEP = KS;
+  // Extra lag of wave w+1 behind wave w.  Data a wave hands over at step p is
+  // read (one step early, by the prefetch) at step p + KS, always in the next
+  // barrier interval.
+  static constexpr int LAG = KS;
+  static constexpr int SH = 4 * KS;                           // handoff rings, tiles
+  // reference tiles in flight: the oldest lane's tile up to the tiles staged
+  // two intervals ahead
+  static constexpr int SPAN = kWave * W + (W - 1) * LAG + 3 * KS + 2;
   static constexpr int SR = pow2_ceil<SPAN>();                // reference ring, tiles
   static constexpr int THREADS = kWave * W;
   static constexpr int ROWS = kWave * R * W;                  // rows per pass
-  static constexpr int CHUNK = KSTEP * T;                     // floats staged per interval
+  static constexpr int CHUNK = KS * T;                        // floats staged per interval
   static constexpr int LDS_FLOATS = SR * T + W * SH * T;
 };
 
-// Stage the reference tiles [tile0, tile0 + KSTEP) and the wave-0 top
-// boundary (zeros on the first pass, the previous pass's last row after it)
-// from global memory into registers.
-template <int R, int T, int W>
+// Stage the reference tiles [tile0, tile0 + KS) and the wave-0 top boundary
+// (zeros on the first pass, the previous pass's last row after it) from
+// global memory into registers; commit them to the LDS rings later.
+template <int R, int T, int W, int KS>
 struct Stager {
-  using S = FwdShape<R, T, W>;
+  using S = FwdShape<R, T, W, KS>;
   static constexpr int PER = (S::CHUNK + S::THREADS - 1) / S::THREADS;
   float ref[PER];
   float top[PER];
@@ -123,149 +129,219 @@ __device__ __forceinline__ int64_t uniform_i64(unsigned long long v) {
   return (int64_t)(((unsigned long long)hi << 32) | lo);
 }
 
+// Per-lane DP state of one pass.
+template <int R, int T>
+struct LaneState {
+  float qv[R];     // query values of the lane's rows
+  float dl[R];     // DP values of the lane's rows at the last column done
+  float bot[T];    // the lane's bottom row over the last tile (feeds lane + 1)
+  float corner;    // top boundary at the column before the current tile
+  int ck_cnt;      // steps until the next checkpoint column
+  int ck_idx;      // next checkpoint index
+};
+
+// Uniform (per wavefront) geometry of one pass.
+struct PassGeom {
+  int wave, lane, row0, n, ntiles, nint;
+  int my_delay, lane0_delay, lane63_delay;   // tile = step - delay
+  int out_delay, out_lane;                   // lane holding the row to store
+  int tiles_per_ckpt;
+  int64_t qoff;
+  float* row;                                // row-buffer slot of the query
+};
+
+// One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
+// the wavefront holding the row to store and that row's register index.
+template <int R, int T, int W, int KS, int KIND, bool CKPT, int OUTK>
+__device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
+                                         const PassGeom& G, const float (&rv)[T],
+                                         const float (&inj)[T], int g, float* s_hand) {
+  using S = FwdShape<R, T, W, KS>;
+  // top boundary: the previous lane's bottom row (DPP), for lane 0 the
+  // handoff ring of this wave
+  float up[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) up[t] = wave_shr1(inj[t], L.bot[t]);
+  float upleft = L.corner;                      // D(row-1, first col - 1)
+  L.corner = up[T - 1];
+  const int tau_out = g - G.out_delay;
+  const bool do_out = OUTK >= 0 && tau_out >= 0 && tau_out < G.ntiles;
+  // The block row by row (measured faster on gfx950 than anti-diagonal
+  // order, which the compiler schedules worse for dual issue).
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    float left = L.dl[k];
+    float diag = upleft;
+    float cur[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float c = local_cost<KIND>(L.qv[k], rv[t]);
+      const float mn = min3(up[t], left, diag);
+      cur[t] = mn + c;
+      diag = up[t];
+      left = cur[t];
+    }
+    upleft = L.dl[k];
+    L.dl[k] = cur[T - 1];
+    if (OUTK == k) {                            // folded once the k loop is unrolled
+      if (do_out && G.lane == G.out_lane) {
+        float* dst = G.row + tau_out * T;
+#pragma unroll
+        for (int t = 0; t < T; ++t) dst[t] = cur[t];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) up[t] = cur[t];
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) L.bot[t] = up[t];
+
+  // lane 63 hands its bottom row to the next wave
+  if (G.wave + 1 < W && G.lane == kWave - 1) {
+    float* hout = s_hand + (G.wave + 1) * S::SH * T + ((g - G.lane63_delay) & (S::SH - 1)) * T;
+#pragma unroll
+    for (int t = 0; t < T; ++t) hout[t] = L.bot[t];
+  }
+
+  if constexpr (CKPT) {
+    // Checkpoint column kc*ckpt_every - 1 is the last column of a tile
+    // (ckpt_every is a multiple of T); a per-lane countdown finds it.
+    if (--L.ck_cnt == 0) {
+      L.ck_cnt = G.tiles_per_ckpt;
+      if (L.ck_idx < p.n_ckpt) {
+        float* dst = p.ckpt + G.qoff * p.n_ckpt + (int64_t)L.ck_idx * G.n + G.row0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          if (G.row0 + k < G.n) dst[k] = L.dl[k];
+      }
+      ++L.ck_idx;
+    }
+  }
+}
+
+// LDS inputs of step g: this lane's reference tile and this wave's top
+// boundary (used by lane 0 only; every lane reads the same address).
+template <int R, int T, int W, int KS>
+__device__ __forceinline__ void step_inputs(float (&rv)[T], float (&inj)[T], int g,
+                                            const PassGeom& G, const float* s_ref,
+                                            const float* s_hand) {
+  using S = FwdShape<R, T, W, KS>;
+  const float* rin = s_ref + ((g - G.my_delay) & (S::SR - 1)) * T;
+  const float* hin = s_hand + G.wave * S::SH * T + ((g - G.lane0_delay) & (S::SH - 1)) * T;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    rv[t] = rin[t];
+    inj[t] = hin[t];
+  }
+}
+
+// All barrier intervals of one pass.  The LDS inputs of step g+1 are read
+// while step g computes (two register sets, the step loop unrolled by two).
+template <int R, int T, int W, int KS, int KIND, bool CKPT, int OUTK>
+__device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
+                                         const PassGeom& G, const float* prev_row,
+                                         float* s_ref, float* s_hand) {
+  const int tid = threadIdx.x;
+  float rvA[T], injA[T], rvB[T], injB[T];
+  step_inputs<R, T, W, KS>(rvA, injA, 0, G, s_ref, s_hand);
+  for (int it = 0; it < G.nint; ++it) {
+    Stager<R, T, W, KS> st;
+    st.load(p.reference, p.ref_len, prev_row, G.ntiles * T, (it + 2) * KS, tid);
+#pragma unroll 1
+    for (int s = 0; s < KS; s += 2) {
+      const int g = it * KS + s;
+      step_inputs<R, T, W, KS>(rvB, injB, g + 1, G, s_ref, s_hand);
+      fwd_step<R, T, W, KS, KIND, CKPT, OUTK>(p, L, G, rvA, injA, g, s_hand);
+      step_inputs<R, T, W, KS>(rvA, injA, g + 2, G, s_ref, s_hand);
+      fwd_step<R, T, W, KS, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand);
+    }
+    st.commit(s_ref, s_hand, (it + 2) * KS, tid);
+    __syncthreads();
+  }
+}
+
+// The wavefront holding the stored row runs a copy of the pass with that
+// row's register index as a compile-time constant; the others store nothing.
+template <int K, int R, int T, int W, int KS, int KIND, bool CKPT>
+__device__ __forceinline__ void fwd_pass_out(int out_k, const FwdParams& p, LaneState<R, T>& L,
+                                             const PassGeom& G, const float* prev_row,
+                                             float* s_ref, float* s_hand) {
+  if constexpr (K < R) {
+    if (out_k == K) {
+      fwd_pass<R, T, W, KS, KIND, CKPT, K>(p, L, G, prev_row, s_ref, s_hand);
+    } else {
+      fwd_pass_out<K + 1, R, T, W, KS, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand);
+    }
+  }
+}
+
 // Process every pass of query b with the team of W waves of this workgroup.
 // `row` is this query's row-buffer slot.
-template <int R, int T, int W, int KIND, bool CKPT>
+template <int R, int T, int W, int KS, int KIND, bool CKPT>
 __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qoff,
                                           float* __restrict__ row, float* s_ref, float* s_hand) {
-  using S = FwdShape<R, T, W>;
-  constexpr int KSTEP = S::KSTEP, LAG = S::LAG, SH = S::SH, SR = S::SR;
+  using S = FwdShape<R, T, W, KS>;
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = wave_id();
-  const int pos = wave * kWave + lane;                 // lane position in the team
-
-  const int n = __builtin_amdgcn_readfirstlane(p.lens[b]);   // uniform: loop bounds below
+  PassGeom G;
+  G.lane = tid & (kWave - 1);
+  G.wave = wave_id();
+  const int pos = G.wave * kWave + G.lane;             // lane position in the team
+  G.n = __builtin_amdgcn_readfirstlane(p.lens[b]);     // uniform: loop bounds below
+  G.qoff = qoff;
+  G.row = row;
   const float* __restrict__ q = p.queries + qoff;
-  const int m = p.ref_len;
-  const int ntiles = (m + T - 1) / T;
-  const int row_len = ntiles * T;
-  const int npass = (n + S::ROWS - 1) / S::ROWS;
-  const int steps = ntiles + kWave * W - 1 + (W - 1) * LAG;
-  const int nint = (steps + KSTEP - 1) / KSTEP;
+  G.ntiles = (p.ref_len + T - 1) / T;
+  const int npass = (G.n + S::ROWS - 1) / S::ROWS;
+  const int steps = G.ntiles + kWave * W - 1 + (W - 1) * S::LAG;
+  G.nint = (steps + KS - 1) / KS;
+  G.my_delay = pos + G.wave * S::LAG;
+  G.lane0_delay = G.wave * (kWave + S::LAG);
+  G.lane63_delay = G.lane0_delay + kWave - 1;
+  G.tiles_per_ckpt = CKPT ? p.ckpt_every / T : 1;
 
   for (int pass = 0; pass < npass; ++pass) {
     const int prow0 = pass * S::ROWS;                  // first row of this pass
-    const int row0 = prow0 + pos * R;                  // first row of this lane
-    float qv[R], dl[R], bot[T];
+    G.row0 = prow0 + pos * R;                          // first row of this lane
+    LaneState<R, T> L;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      qv[k] = (row0 + k < n) ? q[row0 + k] : 0.0f;
-      dl[k] = inf_f32();
+      L.qv[k] = (G.row0 + k < G.n) ? q[G.row0 + k] : 0.0f;
+      L.dl[k] = inf_f32();
     }
 #pragma unroll
-    for (int t = 0; t < T; ++t) bot[t] = inf_f32();
-    float corner = inf_f32();
+    for (int t = 0; t < T; ++t) L.bot[t] = inf_f32();
+    L.corner = inf_f32();
+    L.ck_cnt = G.tiles_per_ckpt + G.my_delay;          // steps until tau = tiles_per_ckpt-1
+    L.ck_idx = 0;
 
     // Row written to the row buffer by this pass: the pass's last row, or
     // row N on the final pass.
     const bool last_pass = pass == npass - 1;
-    const int out_row = last_pass ? (n - 1 - prow0) : (S::ROWS - 1);
+    const int out_row = last_pass ? (G.n - 1 - prow0) : (S::ROWS - 1);
     const int out_pos = out_row / R;
     const int out_k = out_row - out_pos * R;
     const int out_wave = out_pos / kWave;
-    const int out_lane = out_pos - out_wave * kWave;
-    const int out_delay = out_pos + out_wave * LAG;    // out lane's tile = g - out_delay
-    const int my_delay = pos + wave * LAG;
-    const int lane0_delay = wave * (kWave + LAG);      // lane 0 of this wave
-    const int lane63_delay = lane0_delay + kWave - 1;
-    const int tiles_per_ckpt = CKPT ? p.ckpt_every / T : 1;
-    int ck_cnt = tiles_per_ckpt + my_delay;            // steps until tau = tiles_per_ckpt-1
-    int ck_idx = 0;
+    G.out_lane = out_pos - out_wave * kWave;
+    G.out_delay = out_pos + out_wave * S::LAG;          // out lane's tile = step - out_delay
+    const float* prev_row = pass > 0 ? row : nullptr;
 
     // +inf handoff rings (a wave before its first tile must see +inf), then
-    // the first interval of reference and top boundary.
-    for (int e = tid; e < W * SH * T; e += S::THREADS) s_hand[e] = inf_f32();
+    // the first two intervals of reference and top boundary.
+    for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = inf_f32();
     __syncthreads();
     {
-      Stager<R, T, W> st;
-      st.load(p.reference, m, pass > 0 ? row : nullptr, row_len, 0, tid);
-      st.commit(s_ref, s_hand, 0, tid);
+      Stager<R, T, W, KS> st0, st1;
+      st0.load(p.reference, p.ref_len, prev_row, G.ntiles * T, 0, tid);
+      st1.load(p.reference, p.ref_len, prev_row, G.ntiles * T, KS, tid);
+      st0.commit(s_ref, s_hand, 0, tid);
+      st1.commit(s_ref, s_hand, KS, tid);
     }
     __syncthreads();
 
-    for (int it = 0; it < nint; ++it) {
-      Stager<R, T, W> st;
-      st.load(p.reference, m, pass > 0 ? row : nullptr, row_len, (it + 1) * KSTEP, tid);
-
-#pragma unroll 1
-      for (int s = 0; s < KSTEP; ++s) {
-        const int g = it * KSTEP + s;
-        const int tau = g - my_delay;
-        // top boundary of this lane's block: the previous lane's bottom row
-        // (DPP), or for lane 0 the handoff ring of this wave.
-        const int tau0 = g - lane0_delay;
-        const float* hin = s_hand + wave * SH * T + (tau0 & (SH - 1)) * T;
-        const float* rin = s_ref + (tau & (SR - 1)) * T;
-        float top[T], rv[T];
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-          top[t] = wave_shr1(hin[t], bot[t]);
-          rv[t] = rin[t];
-        }
-
-        const int tau_out = g - out_delay;
-        const bool do_out = wave == out_wave && tau_out >= 0 && tau_out < ntiles;
-
-        // R x T block, row by row.
-        float up[T];
-#pragma unroll
-        for (int t = 0; t < T; ++t) up[t] = top[t];
-        float upleft = corner;                          // D(row-1, first col - 1)
-        corner = top[T - 1];
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-          float left = dl[k];
-          float diag = upleft;
-          float cur[T];
-#pragma unroll
-          for (int t = 0; t < T; ++t) {
-            const float c = local_cost<KIND>(qv[k], rv[t]);
-            const float mn = min3(up[t], left, diag);
-            cur[t] = mn + c;
-            diag = up[t];
-            left = cur[t];
-          }
-          upleft = dl[k];
-          dl[k] = cur[T - 1];
-          if (do_out && k == out_k) {
-            if (lane == out_lane) {
-              float* dst = row + tau_out * T;
-#pragma unroll
-              for (int t = 0; t < T; ++t) dst[t] = cur[t];
-            }
-          }
-#pragma unroll
-          for (int t = 0; t < T; ++t) up[t] = cur[t];
-        }
-#pragma unroll
-        for (int t = 0; t < T; ++t) bot[t] = up[t];
-
-        // lane 63 hands its bottom row to the next wave
-        if (wave + 1 < W && lane == kWave - 1) {
-          const int tau63 = g - lane63_delay;
-          float* hout = s_hand + (wave + 1) * SH * T + (tau63 & (SH - 1)) * T;
-#pragma unroll
-          for (int t = 0; t < T; ++t) hout[t] = bot[t];
-        }
-
-        if constexpr (CKPT) {
-          // Checkpoint column kc*ckpt_every - 1 is the last column of a tile
-          // (ckpt_every is a multiple of T); a per-lane countdown finds it.
-          if (--ck_cnt == 0) {
-            ck_cnt = tiles_per_ckpt;
-            if (ck_idx < p.n_ckpt) {
-              float* dst = p.ckpt + qoff * p.n_ckpt + (int64_t)ck_idx * n + row0;
-#pragma unroll
-              for (int k = 0; k < R; ++k)
-                if (row0 + k < n) dst[k] = dl[k];
-            }
-            ++ck_idx;
-          }
-        }
-      }
-      st.commit(s_ref, s_hand, (it + 1) * KSTEP, tid);
-      __syncthreads();
+    if (G.wave == out_wave) {
+      fwd_pass_out<0, R, T, W, KS, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand);
+    } else {
+      fwd_pass<R, T, W, KS, KIND, CKPT, -1>(p, L, G, prev_row, s_ref, s_hand);
     }
   }
 }
@@ -301,13 +377,13 @@ __device__ __forceinline__ void finish_query(const FwdParams& p, int b, const fl
 }
 
 // One workgroup per query.
-template <int R, int T, int W, int KIND, bool CKPT>
+template <int R, int T, int W, int KS, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) {
-  using S = FwdShape<R, T, W>;
+  using S = FwdShape<R, T, W, KS>;
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   const int b = blockIdx.x;
   float* row = p.rowbuf + (int64_t)b * p.row_stride;
-  fwd_query<R, T, W, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T);
+  fwd_query<R, T, W, KS, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T);
   finish_query(p, b, row);
 }
 
@@ -315,9 +391,9 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) 
 // first) from a device counter; each workgroup owns one row-buffer slot and
 // reduces each finished query's last row in place.  Every workgroup leaves
 // the loop once the counter passes the batch size.
-template <int R, int T, int W, int KIND, bool CKPT>
+template <int R, int T, int W, int KS, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const FwdParams p) {
-  using S = FwdShape<R, T, W>;
+  using S = FwdShape<R, T, W, KS>;
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   __shared__ int s_item;
   float* row = p.rowbuf + (int64_t)blockIdx.x * p.row_stride;
@@ -336,7 +412,7 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const Fw
     __syncthreads();
     if (item >= p.batch) break;
     const int b = __builtin_amdgcn_readfirstlane(p.order[item]);
-    fwd_query<R, T, W, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T);
+    fwd_query<R, T, W, KS, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T);
     finish_query(p, b, row);
   }
 }

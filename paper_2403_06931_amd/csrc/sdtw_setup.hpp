@@ -1,0 +1,76 @@
+// sdtw_setup.hpp -- small one-workgroup kernels that run before the DP
+// kernels: the query offset table and the processing order of the
+// persistent form.  Included by the API translation unit only.
+#pragma once
+
+#include "sdtw_common.hpp"
+
+namespace sdtw {
+
+// Exclusive prefix sum of the query lengths (offsets[0..batch]) in one
+// workgroup: each thread sums a contiguous chunk, the chunk sums are scanned
+// in LDS, then each thread writes its chunk's offsets.
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void sdtw_offsets_kernel(
+    const int32_t* __restrict__ lens, int32_t batch, int64_t* __restrict__ offsets) {
+  __shared__ int64_t s_sum[kScanThreads];
+  const int tid = threadIdx.x;
+  const int per = (batch + kScanThreads - 1) / kScanThreads;
+  const int lo = min(batch, tid * per), hi = min(batch, lo + per);
+  int64_t acc = 0;
+  for (int i = lo; i < hi; ++i) acc += lens[i];
+  s_sum[tid] = acc;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const int64_t v = tid >= d ? s_sum[tid - d] : 0;
+    __syncthreads();
+    s_sum[tid] += v;
+    __syncthreads();
+  }
+  int64_t run = s_sum[tid] - acc;                      // exclusive prefix of this chunk
+  for (int i = lo; i < hi; ++i) {
+    offsets[i] = run;
+    run += lens[i];
+  }
+  if (tid == kScanThreads - 1) offsets[batch] = s_sum[tid];
+}
+
+// Processing order for the persistent form: queries sorted by the number
+// of row passes they need (most first), so the longest work starts first and
+// the short queries fill the tail.  Queries with equal pass counts are
+// placed in an unspecified order; results do not depend on the order.  Also
+// zeroes the work counter (a kernel, not a memset, so the sequence is safe to
+// capture in a graph and replay).
+constexpr int kOrderBins = 4096;
+
+__global__ __launch_bounds__(kScanThreads) void sdtw_order_kernel(
+    const int32_t* __restrict__ lens, int32_t batch, int32_t rows_per_pass,
+    int32_t* __restrict__ order, int32_t* __restrict__ queue) {
+  __shared__ int32_t s_cnt[kOrderBins];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kOrderBins; i += kScanThreads) s_cnt[i] = 0;
+  if (tid == 0) queue[0] = 0;
+  __syncthreads();
+  for (int b = tid; b < batch; b += kScanThreads) {
+    const int passes = min(kOrderBins - 1, (lens[b] + rows_per_pass - 1) / rows_per_pass);
+    atomicAdd(&s_cnt[kOrderBins - 1 - passes], 1);     // descending by passes
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < kOrderBins; ++i) {
+      const int c = s_cnt[i];
+      s_cnt[i] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int b = tid; b < batch; b += kScanThreads) {
+    const int passes = min(kOrderBins - 1, (lens[b] + rows_per_pass - 1) / rows_per_pass);
+    const int at = atomicAdd(&s_cnt[kOrderBins - 1 - passes], 1);
+    order[at] = b;
+  }
+}
+
+}  // namespace sdtw
