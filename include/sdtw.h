@@ -95,9 +95,10 @@ SDTW_API size_t sdtw_forward_workspace_bytes(const int32_t *h_query_lens, int32_
 
 /*
  * Number of float32 entries of the checkpoint buffer for this batch and
- * checkpoint interval: sum_b len_b * ceil(ref_len / ckpt_every - 1).
- * Layout: query b's block starts at offset(b) * n_ckpt, where
- * n_ckpt = ceil(ref_len / ckpt_every) - 1, and holds n_ckpt columns of len_b
+ * checkpoint interval: n_ckpt * sum_b len_b, where
+ * n_ckpt = ceil(ref_len / ckpt_every) - 1.
+ * Layout: query b's block starts at offset(b) * n_ckpt (offset(b) = sum of
+ * the lengths of queries 0..b-1) and holds n_ckpt columns of len_b
  * values each; column k (k = 1..n_ckpt) is D(1..len_b, k*ckpt_every), i.e. the
  * DP column of 0-based reference index k*ckpt_every - 1.
  * Returns 0 if no checkpoint is needed (ref_len <= ckpt_every) or on invalid
@@ -120,8 +121,8 @@ SDTW_API size_t sdtw_checkpoint_floats(const int32_t *h_query_lens, int32_t batc
  *   ckpt         device float32 [sdtw_checkpoint_floats(...)] when flags has
  *                SDTW_F_CHECKPOINT (may be NULL if that count is 0), else
  *                ignored
- *   ckpt_every   checkpoint interval in reference columns (>= 1) when
- *                checkpointing, else ignored
+ *   ckpt_every   checkpoint interval in reference columns, a positive
+ *                multiple of 16, when checkpointing, else ignored
  *   variant      kernel tile variant (0 <= variant < sdtw_variant_count()),
  *                or -1 to let the library choose
  *   workspace    device, >= sdtw_forward_workspace_bytes(...) bytes,
@@ -136,8 +137,11 @@ SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
                  void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Bytes of device workspace sdtw_backward needs.  Returns 0 on invalid
- * arguments.
+ * Bytes of device workspace sdtw_backward needs: per-query reference
+ * partials (batch x ref_len floats), per-row path bounds, and 2-bit direction
+ * codes for the blocks recomputed at once (up to 8 blocks of ckpt_every
+ * columns per query, fewer when that would exceed 1 GiB, at least one).
+ * Returns 0 on invalid arguments or when a query is longer than 8,192 rows.
  */
 SDTW_API size_t sdtw_backward_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
                                      int64_t ref_len, int32_t ckpt_every);
@@ -148,7 +152,8 @@ SDTW_API size_t sdtw_backward_workspace_bytes(const int32_t *h_query_lens, int32
  * (N, end_pos + 1) to row 1; on ties the walk prefers the diagonal, then the
  * cell above, then the cell to the left.  DP blocks of ckpt_every columns are
  * recomputed from the checkpoints stored by sdtw_forward (same queries,
- * reference, cost kind and ckpt_every, with SDTW_F_CHECKPOINT).
+ * reference, cost kind and ckpt_every, with SDTW_F_CHECKPOINT).  Queries may
+ * be at most 8,192 rows long (SDTW_ERR_UNSUPPORTED otherwise).
  *
  * For every path cell (i,j) of query b, term = grad_cost[b] * c'(q_i - r_j)
  * with c'(t) = 2t (squared) or sign(t), sign(0) = 0 (absolute):
@@ -165,6 +170,9 @@ SDTW_API size_t sdtw_backward_workspace_bytes(const int32_t *h_query_lens, int32
  *                   when sdtw_checkpoint_floats(...) is 0)
  *   grad_queries    device float32, packed like queries (output)
  *   grad_reference  device float32 [ref_len] (output)
+ *   workspace       device, >= sdtw_backward_workspace_bytes(...) bytes,
+ *                   256-byte aligned
+ *   stream          hipStream_t or NULL
  */
 SDTW_API int sdtw_backward(const float *queries, const int32_t *h_query_lens,
                   const int32_t *query_lens, int32_t batch,

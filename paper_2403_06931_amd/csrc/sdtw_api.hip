@@ -157,41 +157,42 @@ int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t 
   return best;
 }
 
-// Backward: wavefronts per query from the longest query (directions for
-// 64*W lanes x rows must fit the 128 KiB LDS buffer); 0 = unsupported.
-int bwd_waves(int32_t nmax) {
-  if (nmax <= sdtw::BwdShape<4>::MAX_ROWS) return 4;
-  if (nmax <= sdtw::BwdShape<2>::MAX_ROWS) return 2;
-  if (nmax <= sdtw::BwdShape<1>::MAX_ROWS) return 1;
-  return 0;
-}
-
-const void* bwd_kernel(int w, int kind) {
-  if (w == 4) return kind == 0 ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<4, 0>)
-                               : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<4, 1>);
-  if (w == 2) return kind == 0 ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<2, 0>)
-                               : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<2, 1>);
-  return kind == 0 ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<1, 0>)
-                   : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_kernel<1, 1>);
-}
+// Backward: direction codes of `slots` blocks per query are held at once
+// (one round); the code buffer is kept under kBwdCodeBudget bytes where the
+// batch allows, with at least one block per round.
+constexpr size_t kBwdCodeBudget = size_t(1) << 30;
 
 struct BwdLayout {
-  size_t offsets, part, lo, colbuf, total;
+  size_t offsets, state, lo, row_lo, row_hi, part, codes, total;
+  int32_t nseg, slots, rounds;
 };
 
-BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t ckpt_every,
-                     int w) {
+BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t ckpt_every) {
   BwdLayout L{};
+  L.nseg = (ckpt_every + sdtw::kDirSeg - 1) / sdtw::kDirSeg;
+  const size_t words_per_slot =
+      (size_t)L.nseg * sdtw::kWave * ((size_t)total_len + (size_t)(sdtw::kWave - 1) * batch);
+  const size_t bytes_per_slot = words_per_slot * sizeof(uint32_t);
+  const int64_t nblk = (ref_len + ckpt_every - 1) / ckpt_every;
+  int64_t slots = (int64_t)(kBwdCodeBudget / bytes_per_slot);
+  slots = std::max<int64_t>(1, std::min<int64_t>({slots, sdtw::kBwdMaxSlots, nblk}));
+  L.slots = (int32_t)slots;
+  L.rounds = (int32_t)((nblk + slots - 1) / slots);
   size_t at = 0;
   L.offsets = at;
   at = align_up(at + sizeof(int64_t) * ((size_t)batch + 1), kAlign);
+  L.state = at;
+  at = align_up(at + sizeof(int32_t) * 4 * (size_t)batch, kAlign);
   L.lo = at;
   at = align_up(at + sizeof(int32_t) * (size_t)batch, kAlign);
+  L.row_lo = at;
+  at = align_up(at + sizeof(int32_t) * (size_t)total_len, kAlign);
+  L.row_hi = at;
+  at = align_up(at + sizeof(int32_t) * (size_t)total_len, kAlign);
   L.part = at;
   at = align_up(at + sizeof(float) * (size_t)batch * (size_t)row_stride_floats(ref_len), kAlign);
-  L.colbuf = at;
-  const int64_t seg_per_block = (ckpt_every + 256 * w - 1) / (256 * w);
-  at = align_up(at + sizeof(float) * (size_t)total_len * (size_t)seg_per_block, kAlign);
+  L.codes = at;
+  at = align_up(at + bytes_per_slot * (size_t)slots, kAlign);
   L.total = at;
   return L;
 }
@@ -336,11 +337,11 @@ size_t sdtw_backward_workspace_bytes(const int32_t* h_query_lens, int32_t batch,
                                      int32_t ckpt_every) {
   int64_t total = 0;
   int32_t nmax = 0;
-  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len) || ckpt_every < 1)
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len) || ckpt_every < 1 ||
+      ckpt_every % kCkptQuantum != 0)
     return 0;
-  const int w = bwd_waves(nmax);
-  if (w == 0) return 0;
-  return bwd_layout(batch, total, ref_len, ckpt_every, w).total;
+  if (nmax > sdtw::kDirMaxRows) return 0;
+  return bwd_layout(batch, total, ref_len, ckpt_every).total;
 }
 
 int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
@@ -361,17 +362,17 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
   const int64_t nck = n_ckpt_of(ref_len, ckpt_every);
   if (nck > 0 && ckpt == nullptr) return SDTW_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
-  const int w = bwd_waves(nmax);
-  if (w == 0) return SDTW_ERR_UNSUPPORTED;
-  const BwdLayout L = bwd_layout(batch, total, ref_len, ckpt_every, w);
+  if (nmax > sdtw::kDirMaxRows) return SDTW_ERR_UNSUPPORTED;
+  const BwdLayout L = bwd_layout(batch, total, ref_len, ckpt_every);
   if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
 
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   char* ws = static_cast<char*>(workspace);
+  int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
   sdtw::BwdParams p{};
   p.queries = queries;
   p.lens = query_lens;
-  p.offsets = nullptr;
+  p.offsets = offs;
   p.reference = reference;
   p.grad_cost = grad_cost;
   p.end_pos = end_pos;
@@ -379,26 +380,54 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
   p.grad_q = grad_queries;
   p.ref_part = reinterpret_cast<float*>(ws + L.part);
   p.path_lo = reinterpret_cast<int32_t*>(ws + L.lo);
-  p.colbuf = reinterpret_cast<float*>(ws + L.colbuf);
+  p.row_lo = reinterpret_cast<int32_t*>(ws + L.row_lo);
+  p.row_hi = reinterpret_cast<int32_t*>(ws + L.row_hi);
+  p.state = reinterpret_cast<int32_t*>(ws + L.state);
+  p.codes = reinterpret_cast<uint32_t*>(ws + L.codes);
   p.part_stride = row_stride_floats(ref_len);
   p.batch = batch;
   p.ref_len = (int32_t)ref_len;
   p.ckpt_every = ckpt_every;
   p.n_ckpt = (int32_t)nck;
-  p.seg_per_block = (ckpt_every + 256 * w - 1) / (256 * w);
+  p.nseg = L.nseg;
+  p.slots = L.slots;
+  p.max_rows = nmax;
+  p.round = 0;
 
-  if (batch > kInKernelOffsetBatch) {
-    int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
+  int rc;
+  {
     void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
-    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
-                    dim3(sdtw::kScanThreads), args, stream);
+    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
+                dim3(sdtw::kScanThreads), args, stream);
     if (rc != SDTW_OK) return rc;
-    p.offsets = offs;
   }
   {
-    const void* fn = bwd_kernel(w, cost_kind);
     void* args[] = {(void*)&p};
-    int rc = launch(fn, dim3(batch), dim3(64 * w), args, stream);
+    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_bwd_init_kernel),
+                dim3((batch + sdtw::kInitThreads - 1) / sdtw::kInitThreads),
+                dim3(sdtw::kInitThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  const void* dirs = cost_kind == SDTW_COST_SQUARED
+                         ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
+                         : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
+  const size_t dirs_lds = sizeof(float) * 2 * (size_t)nmax;
+  for (int r = 0; r < L.rounds; ++r) {
+    p.round = r;
+    void* args[] = {(void*)&p};
+    if (hipLaunchKernel(dirs, dim3(batch, L.slots), dim3(sdtw::kWave), args, dirs_lds, stream) !=
+        hipSuccess)
+      return SDTW_ERR_HIP;
+    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_bwd_walk_kernel), dim3(batch),
+                dim3(sdtw::kWave), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  {
+    const void* grad = cost_kind == SDTW_COST_SQUARED
+                           ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<0>)
+                           : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1>);
+    void* args[] = {(void*)&p};
+    rc = launch(grad, dim3(batch), dim3(sdtw::kGradThreads), args, stream);
     if (rc != SDTW_OK) return rc;
   }
   {

@@ -8,169 +8,93 @@
 // locally constant, so d cost / d q_i and d cost / d r_j are sums of the
 // local-cost derivative over the path cells in row i / column j.
 //
-// Memory: the forward stored D(1..N, k*K) for every K-th column (K =
-// ckpt_every).  One workgroup per query walks its path block by block, from
-// the block holding end_pos leftwards, without ever holding the N x M matrix:
+// The forward stored D(1..N, k*K) for every K-th column (K = ckpt_every), so
+// every block of K columns can be recomputed on its own.  The backward runs
+// in rounds, each covering the next G blocks of every unfinished query, from
+// the block holding end_pos leftwards:
 //
-//   phase 1  recompute the block from its left checkpoint, rows 1..i (i the
-//            path's current row), keeping only the last column of every
-//            S-column segment (global scratch);
-//   phase 2  for each segment the path enters, right to left: recompute it
-//            from its left column, writing a 2-bit direction code per cell
-//            into LDS (S x rows fits in 128 KiB), then wave 0 walks it.
+//   dirs   one wavefront per (query, block): recompute the block from its
+//          left checkpoint and store a 2-bit direction code per cell to a
+//          global scratch buffer (all blocks of the round in parallel);
+//   walk   one wavefront per query: follow the codes from the current cell,
+//          recording for every row the first and last column of the path in
+//          that row; stop at row 1 or when the round's blocks are used up.
 //
-// The recompute uses the column-owning mapping of the paper's Section 5.2
-// kernel, which suits these narrow, tall segments: lane L owns 4 adjacent
-// reference columns and walks down the rows, one row per step, one step
-// behind lane L-1; a lane's right-most value reaches lane L+1 through a DPP
-// wave_shr:1 move, and wave w's lane 63 hands it to wave w+1 through an LDS
-// ring (one barrier every KSTEP steps, wave w+1 lagging by KSTEP-1 extra
-// steps, as in the forward kernel).  Each cell is recomputed with exactly the
-// forward's operations, so the recomputed values are bit-identical.
+// A final kernel forms the gradients from the recorded rows: the path cells
+// of one row are a run of columns and those of one column a run of rows, so
+// every row sum and every column sum is an independent sequential sum, added
+// in walk order (columns descending within a row, rows descending within a
+// column).  Another kernel adds the per-query reference partials in
+// increasing query order.
 //
-// Gradient accumulation (matches the walk order of the definition in
-// include/sdtw.h): the walker keeps the running sum of the current row
-// (query gradient) and of the current column (per-query reference partial)
-// and stores each when the path leaves that row / column.  A second kernel
-// adds the per-query reference partials in increasing query order.
+// Recompute mapping (the column-owning layout of the paper's Section 5.2
+// kernel, which suits these narrow, tall blocks): lane l owns 16 adjacent
+// reference columns of a 1024-column segment and walks down the rows, one row
+// per step, one step behind lane l-1; lane l-1's right-most value reaches lane
+// l through a DPP wave_shr:1 move, and so does the query value of the row.
+// Each cell is recomputed with exactly the forward's operations, so the
+// recomputed values and the directions taken from them are those of the
+// full matrix.
 #pragma once
 
 #include "sdtw_common.hpp"
 
 namespace sdtw {
 
+constexpr int kDirCols = 16;                    // reference columns per lane
+constexpr int kDirSeg = kWave * kDirCols;       // columns per segment
+constexpr int kDirMaxRows = 8192;               // query + left column held in LDS
+constexpr int kWalkChunk = 64;                  // code rows per walker LDS chunk
+constexpr int kBwdMaxSlots = 8;                 // blocks per round per query
+
+// Direction codes (2 bits per cell; cell c of a word at bits 2c, 2c+1).
+constexpr uint32_t kDirDiag = 0;
+constexpr uint32_t kDirUp = 1;
+constexpr uint32_t kDirLeft = 2;
+
 struct BwdParams {
   const float* queries;       // packed
   const int32_t* lens;        // [batch]
-  const int64_t* offsets;     // [batch + 1] or nullptr (summed in-kernel)
+  const int64_t* offsets;     // [batch + 1]
   const float* reference;     // [ref_len]
   const float* grad_cost;     // [batch]
   const int64_t* end_pos;     // [batch]
-  const float* ckpt;          // forward checkpoints (may be nullptr if n_ckpt == 0)
+  const float* ckpt;          // forward checkpoints (nullptr when n_ckpt == 0)
   float* grad_q;              // packed like queries
   float* ref_part;            // [batch][part_stride] per-query reference partials
   int32_t* path_lo;           // [batch] first reference column of the path
-  float* colbuf;              // segment boundary columns: query b at offset(b) * seg_per_block
+  int32_t* row_lo;            // packed like queries: first path column of each row
+  int32_t* row_hi;            // packed like queries: last path column of each row
+  int32_t* state;             // [batch][4]: current row (1-based), column, done
+  uint32_t* codes;            // direction words, see code_segment()
   int64_t part_stride;
   int32_t batch;
   int32_t ref_len;
   int32_t ckpt_every;
   int32_t n_ckpt;
-  int32_t seg_per_block;      // ceil(ckpt_every / S)
+  int32_t nseg;               // segments per block, ceil(ckpt_every / kDirSeg)
+  int32_t slots;              // blocks per round (G)
+  int32_t max_rows;           // longest query (sizes the dirs kernel's LDS)
+  int32_t round;
 };
-
-constexpr int kBwdCols = 4;                 // reference columns per lane
-constexpr int kBwdDirBytes = 131072;        // LDS for direction codes
-constexpr int kBwdStepsPerBarrier = 8;
-
-template <int W>
-struct BwdShape {
-  static constexpr int THREADS = kWave * W;
-  static constexpr int S = THREADS * kBwdCols;              // segment width (columns)
-  static constexpr int MAX_ROWS = kBwdDirBytes / THREADS;   // one byte per lane per row
-  static constexpr int KSTEP = kBwdStepsPerBarrier;
-  static constexpr int LAG = KSTEP - 1;
-  static constexpr int SH = 2 * KSTEP;                      // handoff ring (rows)
-};
-
-// Direction codes (2 bits).
-constexpr int kDirDiag = 0;
-constexpr int kDirUp = 1;
-constexpr int kDirLeft = 2;
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Shared memory of the backward kernel.
-template <int W>
-struct BwdSmem {
-  using S = BwdShape<W>;
-  uint8_t dirs[kBwdDirBytes];                 // [row - 1][lane]: 4 codes, 2 bits each
-  float q[S::MAX_ROWS];                       // this query's values
-  float left[S::MAX_ROWS];                    // left boundary column of the segment
-  float rseg[S::S];                           // reference values of the segment
-  float ring[W][S::SH];                       // wave -> wave handoff of the right edge
-  int state[4];                               // walker -> team: i, j, done
-};
+__device__ __forceinline__ int64_t wave_uniform64(int64_t v) {
+  const unsigned long long u = (unsigned long long)v;
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(u >> 32));
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(u & 0xffffffffu));
+  return (int64_t)(((unsigned long long)hi << 32) | lo);
+}
 
-// Recompute rows 1..nrows of the segment [c0, c0 + ncols) (ncols <= S).
-// Inputs in LDS: sm.q (query), sm.left (D(i, c0-1), i = 1..nrows; +inf when
-// c0 is the first column of the reference), sm.rseg (reference values, zero
-// past the segment).  Row 0 is the free-start zero row.
-// DIRS: write each cell's direction code to sm.dirs.
-// RIGHT: write D(i, c0 + S - 1) to right[i - 1] (full segments only).
-template <int W, int KIND, bool DIRS, bool RIGHT>
-__device__ __forceinline__ void seg_dp(BwdSmem<W>& sm, int nrows, float* __restrict__ right) {
-  using S = BwdShape<W>;
-  constexpr int C = kBwdCols, KSTEP = S::KSTEP, LAG = S::LAG, SH = S::SH;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = wave_uniform(tid / kWave);
-  const int pos = wave * kWave + lane;
-  const int delay = pos + wave * LAG;
-  const int lane0_delay = wave * (kWave + LAG);
-  const int lane63_delay = lane0_delay + kWave - 1;
-
-  float rv[C];
-#pragma unroll
-  for (int c = 0; c < C; ++c) rv[c] = sm.rseg[pos * C + c];
-  float dprev[C];                               // row i-1 of this lane's columns
-#pragma unroll
-  for (int c = 0; c < C; ++c) dprev[c] = 0.0f;  // row 0
-  float last = 0.0f;                            // this lane's right-most value, last row done
-  float shp = 0.0f;                             // left neighbour's value one row up
-
-  for (int e = tid; e < W * SH; e += S::THREADS) (&sm.ring[0][0])[e] = 0.0f;
-  __syncthreads();
-
-  const int steps = nrows + kWave * W - 1 + (W - 1) * LAG;
-  const int nint = (steps + KSTEP - 1) / KSTEP;
-  for (int it = 0; it < nint; ++it) {
-#pragma unroll 1
-    for (int s = 0; s < KSTEP; ++s) {
-      const int g = it * KSTEP + s;
-      const int i = g - delay + 1;              // row of this lane at this step
-      // left neighbour's value on row i: DPP from lane-1, or for lane 0 the
-      // segment's left column (wave 0) / the previous wave's ring.
-      const int i0 = g - lane0_delay + 1;       // row of lane 0 of this wave
-      float inj;
-      if (wave == 0) {
-        inj = (i0 >= 1 && i0 <= nrows) ? sm.left[i0 - 1] : 0.0f;
-      } else {
-        inj = sm.ring[wave][i0 & (SH - 1)];
-      }
-      const float shc = wave_shr1(inj, last);
-      if (i >= 1 && i <= nrows) {
-        const float qi = sm.q[i - 1];
-        float cur[C];
-        uint32_t code = 0;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-          const float up = dprev[c];
-          const float left = c == 0 ? shc : cur[c - 1];
-          const float diag = c == 0 ? shp : dprev[c - 1];
-          const float mn = min3(up, left, diag);
-          if constexpr (DIRS) {
-            const uint32_t dcode = diag == mn ? kDirDiag : (up == mn ? kDirUp : kDirLeft);
-            code |= dcode << (2 * c);
-          }
-          cur[c] = mn + local_cost<KIND>(qi, rv[c]);
-        }
-        if constexpr (DIRS) sm.dirs[(i - 1) * S::THREADS + pos] = (uint8_t)code;
-        if constexpr (RIGHT) {
-          if (pos == S::THREADS - 1) right[i - 1] = cur[C - 1];
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) dprev[c] = cur[c];
-        last = cur[C - 1];
-      }
-      shp = shc;
-      if (wave + 1 < W && lane == kWave - 1) {
-        const int i63 = g - lane63_delay + 1;
-        sm.ring[wave + 1][i63 & (SH - 1)] = last;
-      }
-    }
-    __syncthreads();
-  }
+// Codes of segment s of round slot t of query b: n + 63 rows of 64 words;
+// word l of row g holds the 16 codes of lane l at step g, i.e. of query row
+// i = g - l + 1 and columns 16l .. 16l+15 of the segment.
+__device__ __forceinline__ int64_t code_segment(const BwdParams& p, int b, int64_t qoff, int n,
+                                                int t, int s) {
+  const int64_t rows = (int64_t)n + kWave - 1;
+  const int64_t base = (int64_t)p.slots * p.nseg * kWave * (qoff + (int64_t)(kWave - 1) * b);
+  return base + ((int64_t)t * p.nseg + s) * rows * kWave;
 }
 
 // Local-cost derivative with respect to the query value at t = q - r.
@@ -184,142 +108,247 @@ __device__ __forceinline__ float dcost_dq(float q, float r) {
   }
 }
 
-template <int W, int KIND>
-__global__ __launch_bounds__(kWave * W) void sdtw_bwd_kernel(const BwdParams p) {
-  using S = BwdShape<W>;
-  __shared__ BwdSmem<W> sm;
-  __shared__ unsigned long long s_off;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = wave_uniform(tid / kWave);
-  const int b = blockIdx.x;
-  const int n = wave_uniform(p.lens[b]);
-  const int m = p.ref_len;
+// Walker state: start at (N, end_pos); row N's last path column is end_pos.
+constexpr int kInitThreads = 256;
 
-  int64_t qoff;
-  if (p.offsets != nullptr) {
-    qoff = p.offsets[b];
-  } else {
-    if (wave == 0) s_off = 0;
-    __syncthreads();
-    unsigned long long acc = 0;
-    for (int k = tid; k < b; k += S::THREADS) acc += (unsigned long long)p.lens[k];
-    atomicAdd(&s_off, acc);
-    __syncthreads();
-    const unsigned long long v = s_off;
-    qoff = (int64_t)(((unsigned long long)(unsigned)wave_uniform((int)(v >> 32)) << 32) |
-                     (unsigned)wave_uniform((int)(v & 0xffffffffu)));
+__global__ __launch_bounds__(kInitThreads) void sdtw_bwd_init_kernel(const BwdParams p) {
+  const int b = blockIdx.x * kInitThreads + threadIdx.x;
+  if (b >= p.batch) return;
+  const int n = p.lens[b];
+  const int e = (int)p.end_pos[b];
+  p.state[4 * b + 0] = n;
+  p.state[4 * b + 1] = e;
+  p.state[4 * b + 2] = 0;
+  p.state[4 * b + 3] = 0;
+  p.row_hi[p.offsets[b] + n - 1] = e;
+}
+
+// One row step of the direction recompute.  MASKED: some lanes are outside
+// rows 1..nrows and keep their state (row 0 before they start).
+template <int KIND, bool MASKED>
+__device__ __forceinline__ void dirs_step(int g, int lane, int nrows, const float* lq,
+                                          float* ledge, const float (&rv)[kDirCols],
+                                          float (&dprev)[kDirCols], float& last, float& shp,
+                                          float& qv, uint32_t* __restrict__ out) {
+  const int gi = g < nrows ? g : nrows - 1;
+  const float shc = wave_shr1(ledge[gi], last);   // left neighbour on this row
+  qv = wave_shr1(lq[gi], qv);                     // this row's query value
+  float cur[kDirCols];
+  uint32_t word = 0;
+  float left = shc, diag = shp;
+#pragma unroll
+  for (int c = 0; c < kDirCols; ++c) {
+    const float up = dprev[c];
+    const float mn = min3(up, left, diag);
+    const uint32_t code = diag == mn ? kDirDiag : (up == mn ? kDirUp : kDirLeft);
+    word |= code << (2 * c);
+    cur[c] = mn + local_cost<KIND>(qv, rv[c]);
+    diag = up;
+    left = cur[c];
   }
-  const float* __restrict__ q = p.queries + qoff;
-  for (int k = tid; k < n; k += S::THREADS) sm.q[k] = q[k];
+  out[(int64_t)g * kWave] = word;
+  const int i = g - lane + 1;
+  if (!MASKED || (i >= 1 && i <= nrows)) {
+#pragma unroll
+    for (int c = 0; c < kDirCols; ++c) dprev[c] = cur[c];
+    last = cur[kDirCols - 1];
+    // right column of this segment = left column of the next one; entry
+    // i-1 was read by lane 0 at step i-1, 63 steps earlier
+    if (lane == kWave - 1) ledge[i - 1] = last;
+  }
+  shp = shc;
+}
 
-  const float gcost = p.grad_cost[b];
+// Recompute rows 1..i of one block (i = the walker's current row) and store
+// its direction codes.  Grid: (batch, slots); one wavefront per workgroup.
+// Dynamic LDS: query values and the left boundary column, 2 * max_rows floats.
+template <int KIND>
+__global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p) {
+  extern __shared__ float dyn[];
+  const int b = blockIdx.x;
+  const int t = blockIdx.y;
+  const int lane = threadIdx.x;
+  if (wave_uniform(p.state[4 * b + 2]) != 0) return;
   const int K = p.ckpt_every;
-  float* __restrict__ gq = p.grad_q + qoff;
-  float* __restrict__ part = p.ref_part + (int64_t)b * p.part_stride;
-  float* __restrict__ colbuf = p.colbuf + qoff * p.seg_per_block;
-
-  // walker state (uniform; held by wave 0, broadcast through LDS)
-  int pi = n;                                   // current row, 1-based
-  int pj = wave_uniform((int)p.end_pos[b]);     // current column, 0-based
-  float acc_q = 0.0f, acc_r = 0.0f;             // running sums (wave 0)
-  int done = 0;
+  const int64_t e = wave_uniform64(p.end_pos[b]);
+  const int blk_end = (int)(e / K);
+  const int blk = blk_end - p.round * p.slots - t;
+  if (blk < 0) return;
+  const int n = wave_uniform(p.lens[b]);
+  const int nrows = wave_uniform(p.state[4 * b + 0]);
+  const int64_t qoff = wave_uniform64(p.offsets[b]);
+  float* lq = dyn;
+  float* ledge = dyn + p.max_rows;
+  const float* __restrict__ q = p.queries + qoff;
+  const float* ck = blk > 0 ? p.ckpt + qoff * p.n_ckpt + (int64_t)(blk - 1) * n : nullptr;
+  for (int k = lane; k < nrows; k += kWave) {
+    lq[k] = q[k];
+    ledge[k] = blk > 0 ? ck[k] : inf_f32();
+  }
   __syncthreads();
 
-  for (int blk = pj / K; blk >= 0 && !done; --blk) {
-    const int bc0 = blk * K;                    // first column of the block
-    const int nrows = pi;
-    const int seg_last = (pj - bc0) / S::S;     // segment holding the path
-
-    // left boundary of the block: checkpoint blk (column bc0 - 1), or +inf
-    auto load_block_left = [&]() {
-      if (blk == 0) {
-        for (int k = tid; k < nrows; k += S::THREADS) sm.left[k] = inf_f32();
-      } else {
-        const float* ck = p.ckpt + qoff * p.n_ckpt + (int64_t)(blk - 1) * n;
-        for (int k = tid; k < nrows; k += S::THREADS) sm.left[k] = ck[k];
-      }
-    };
-    auto load_seg_ref = [&](int c0) {
-      for (int k = tid; k < S::S; k += S::THREADS) {
-        const int j = c0 + k;
-        sm.rseg[k] = (j < m && j < bc0 + K) ? p.reference[j] : 0.0f;
-      }
-    };
-
-    // phase 1: right columns of the full segments left of the path's segment
-    load_block_left();
-    for (int sg = 0; sg < seg_last; ++sg) {
-      load_seg_ref(bc0 + sg * S::S);
-      __syncthreads();
-      float* right = colbuf + (int64_t)sg * n;
-      seg_dp<W, KIND, false, true>(sm, nrows, right);
-      // next segment's left column = this one's right column
-      __syncthreads();
-      for (int k = tid; k < nrows; k += S::THREADS) sm.left[k] = right[k];
-      __syncthreads();
+  const int bc0 = blk * K;
+  const int bend = bc0 + K < p.ref_len ? bc0 + K : p.ref_len;
+  int nseg = (bend - bc0 + kDirSeg - 1) / kDirSeg;
+  if (blk == blk_end) nseg = (int)(e - bc0) / kDirSeg + 1;   // nothing right of end_pos
+  for (int s = 0; s < nseg; ++s) {
+    const int cs = bc0 + s * kDirSeg;
+    float rv[kDirCols];
+#pragma unroll
+    for (int c = 0; c < kDirCols; ++c) {
+      const int j = cs + lane * kDirCols + c;
+      rv[c] = j < bend ? p.reference[j] : 0.0f;
     }
+    uint32_t* out = p.codes + code_segment(p, b, qoff, n, t, s) + lane;
+    float dprev[kDirCols];
+#pragma unroll
+    for (int c = 0; c < kDirCols; ++c) dprev[c] = 0.0f;      // row 0
+    float last = 0.0f, shp = 0.0f, qv = 0.0f;
+    const int g_end = nrows + kWave - 1;
+    const int g_head = g_end < kWave - 1 ? g_end : kWave - 1;
+    int g = 0;
+    for (; g < g_head; ++g)
+      dirs_step<KIND, true>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+    for (; g < nrows; ++g)
+      dirs_step<KIND, false>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+    for (; g < g_end; ++g)
+      dirs_step<KIND, true>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+  }
+}
 
-    // phase 2: segments right to left, directions + walk
-    for (int sg = seg_last; sg >= 0 && !done; --sg) {
-      const int c0 = bc0 + sg * S::S;
-      if (sg == 0) {
-        load_block_left();
-      } else {
-        const float* right = colbuf + (int64_t)(sg - 1) * n;
-        for (int k = tid; k < pi; k += S::THREADS) sm.left[k] = right[k];
-      }
-      load_seg_ref(c0);
-      __syncthreads();
-      seg_dp<W, KIND, true, false>(sm, pi, nullptr);
-      __syncthreads();
+// Follow the direction codes of this round's blocks.  Grid: batch; one
+// wavefront per workgroup; every lane runs the same (uniform) walk and lane
+// 0 stores.  Code rows are staged through LDS 64 at a time: within a
+// segment the code row g = i - 1 + (lane owning column j) never increases
+// along the walk.
+__global__ __launch_bounds__(kWave) void sdtw_bwd_walk_kernel(const BwdParams p) {
+  __shared__ uint32_t chunk[kWalkChunk * kWave];
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (wave_uniform(p.state[4 * b + 2]) != 0) return;
+  int i = wave_uniform(p.state[4 * b + 0]);
+  int j = wave_uniform(p.state[4 * b + 1]);
+  const int n = wave_uniform(p.lens[b]);
+  const int64_t qoff = wave_uniform64(p.offsets[b]);
+  const int K = p.ckpt_every;
+  const int blk_end = (int)(wave_uniform64(p.end_pos[b]) / K);
+  int32_t* rlo = p.row_lo + qoff - 1;           // indexed by 1-based row
+  int32_t* rhi = p.row_hi + qoff - 1;
+  const int code_rows = n + kWave - 1;
+  int done = 0;
 
-      if (wave == 0) {
-        // every lane of wave 0 walks the same path (uniform values); lane 0
-        // stores
-        int i = pi, j = pj;
-        for (;;) {
-          const float qv = sm.q[i - 1];
-          const float rv = sm.rseg[j - c0];
-          const float term = gcost * dcost_dq<KIND>(qv, rv);
-          acc_q = acc_q + term;
-          acc_r = acc_r + (-term);
-          if (i == 1) {
-            if (lane == 0) {
-              gq[0] = acc_q;
-              part[j] = acc_r;
-              p.path_lo[b] = j;
-            }
-            done = 1;
-            break;
+  for (int t = 0; t < p.slots && !done; ++t) {
+    const int blk = blk_end - p.round * p.slots - t;
+    if (blk < 0) break;
+    const int bc0 = blk * K;
+    for (int s = (j - bc0) / kDirSeg; s >= 0 && !done; --s) {
+      const int cs = bc0 + s * kDirSeg;
+      const uint32_t* seg = p.codes + code_segment(p, b, qoff, n, t, s);
+      int kc = -1;                              // code chunk held in LDS
+      while (j >= cs) {
+        const int L = (j - cs) >> 4;
+        const int c = (j - cs) & (kDirCols - 1);
+        const int g = i - 1 + L;
+        const int k = g / kWalkChunk;
+        if (k != kc) {
+          // stage code rows [64k, 64k + 64); rows past the segment's end
+          // are never addressed
+          __builtin_amdgcn_wave_barrier();
+          for (int m = 0; m < kWalkChunk; ++m) {
+            const int row = k * kWalkChunk + m;
+            if (row < code_rows) chunk[m * kWave + lane] = seg[(int64_t)row * kWave + lane];
           }
-          const int col = j - c0;
-          const int byte = sm.dirs[(i - 1) * S::THREADS + (col >> 2)];
-          const int code = wave_uniform((byte >> (2 * (col & 3))) & 3);
-          if (code != kDirLeft) {               // diagonal or up: leave row i
-            if (lane == 0) gq[i - 1] = acc_q;
-            acc_q = 0.0f;
-            i -= 1;
-          }
-          if (code != kDirUp) {                 // diagonal or left: leave column j
-            if (lane == 0) part[j] = acc_r;
-            acc_r = 0.0f;
-            j -= 1;
-          }
-          if (j < c0) break;
+          __builtin_amdgcn_wave_barrier();
+          kc = k;
         }
-        if (lane == 0) {
-          sm.state[0] = i;
-          sm.state[1] = j;
-          sm.state[2] = done;
+        const uint32_t w =
+            (uint32_t)wave_uniform((int)chunk[(g - k * kWalkChunk) * kWave + L]);
+        // pass through the cells c, c-1, ... of this word whose code is
+        // "left"; the first other one ends the run in this row
+        const uint32_t is_left = (w >> 1) & ~w & 0x55555555u;
+        const uint32_t upto = c == kDirCols - 1 ? 0xffffffffu : ((1u << (2 * c + 2)) - 1u);
+        const uint32_t stop = ~is_left & 0x55555555u & upto;
+        if (stop == 0) {
+          j -= c + 1;                           // into the previous lane's columns
+          continue;
         }
+        const int bit = 31 - __builtin_clz(stop);
+        j -= c - (bit >> 1);
+        if (i == 1) {                           // the start cell
+          if (lane == 0) {
+            rlo[1] = j;
+            p.path_lo[b] = j;
+          }
+          done = 1;
+          break;
+        }
+        const uint32_t code = (w >> bit) & 3u;
+        if (lane == 0) rlo[i] = j;
+        i -= 1;
+        if (code == kDirDiag) j -= 1;
+        if (lane == 0) rhi[i] = j;
       }
-      __syncthreads();
-      pi = wave_uniform(sm.state[0]);
-      pj = wave_uniform(sm.state[1]);
-      done = wave_uniform(sm.state[2]);
-      __syncthreads();
     }
+  }
+  if (lane == 0) {
+    p.state[4 * b + 0] = i;
+    p.state[4 * b + 1] = j;
+    p.state[4 * b + 2] = done;
+  }
+}
+
+// Gradients from the recorded path rows.  Grid: batch; kGradThreads threads.
+//   grad_q[i]      = sum over the row's path columns j (descending) of g*dc/dq
+//   ref_part[b][j] = sum over the column's path rows i (descending) of -g*dc/dq
+// for j in [path_lo, end_pos].  Row i's columns are [row_lo[i], row_hi[i]];
+// both bounds are nondecreasing in i, so column j's rows are found by binary
+// search.
+constexpr int kGradThreads = 256;
+
+template <int KIND>
+__global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdParams p) {
+  const int b = blockIdx.x;
+  const int n = p.lens[b];
+  const int64_t qoff = p.offsets[b];
+  const float* __restrict__ q = p.queries + qoff;
+  const float* __restrict__ r = p.reference;
+  const int32_t* __restrict__ rlo = p.row_lo + qoff - 1;
+  const int32_t* __restrict__ rhi = p.row_hi + qoff - 1;
+  const float gcost = p.grad_cost[b];
+  float* __restrict__ gq = p.grad_q + qoff;
+  float* __restrict__ part = p.ref_part + (int64_t)b * p.part_stride;
+
+  // (the clamps only keep every access in bounds; a finished walk records
+  // every row, with columns in [0, end_pos])
+  const int jhi = (int)p.end_pos[b];
+  for (int i = 1 + (int)threadIdx.x; i <= n; i += kGradThreads) {
+    const float qi = q[i - 1];
+    const int lo = rlo[i] > 0 ? rlo[i] : 0;
+    const int hi = rhi[i] < jhi ? rhi[i] : jhi;
+    float acc = 0.0f;
+    for (int jj = hi; jj >= lo; --jj) acc = acc + gcost * dcost_dq<KIND>(qi, r[jj]);
+    gq[i - 1] = acc;
+  }
+
+  const int jlo = p.path_lo[b] > 0 ? p.path_lo[b] : 0;
+  for (int jj = jlo + (int)threadIdx.x; jj <= jhi; jj += kGradThreads) {
+    int a = 1, z = n;                           // first row whose last column reaches jj
+    while (a < z) {
+      const int mid = (a + z) >> 1;
+      if (rhi[mid] >= jj) z = mid; else a = mid + 1;
+    }
+    const int top = a;
+    z = n;                                      // last row whose first column is <= jj
+    while (a < z) {
+      const int mid = (a + z + 1) >> 1;
+      if (rlo[mid] <= jj) a = mid; else z = mid - 1;
+    }
+    const int bottom = a;
+    const float rj = r[jj];
+    float acc = 0.0f;
+    for (int ii = bottom; ii >= top; --ii)
+      acc = acc + (-(gcost * dcost_dq<KIND>(q[ii - 1], rj)));
+    part[jj] = acc;
   }
 }
 

@@ -133,13 +133,19 @@ def test_backward_rejects_invalid_arguments(L):
     assert _bwd(L, [3, 4], every=24) == E
     assert _bwd(L, [3, 4], ref_len=1000, every=64, ckpt=0) == E   # checkpoints needed
     assert _bwd(L, [3, 4], ws_bytes=8) == L.SDTW_ERR_WORKSPACE
-    assert _bwd(L, [5000], ref_len=100) == L.SDTW_ERR_UNSUPPORTED   # longer than 2,048 rows
+    assert _bwd(L, [8193], ref_len=100) == L.SDTW_ERR_UNSUPPORTED   # longer than 8,192 rows
     assert _bwd(L, [3, 4], ws=FAKE + 8) == E
 
 
 def test_backward_workspace_sizes(L):
     import paper_2403_06931_amd as P
     lens = np.array([100, 1000, 2048], np.int32)
-    assert P.sdtw_backward_workspace_bytes(lens, 50000, 1024) >= 3 * 50000 * 4
-    assert P.sdtw_backward_workspace_bytes(np.array([2049], np.int32), 100, 64) == 0
+    ws = P.sdtw_backward_workspace_bytes(lens, 50000, 1024)
+    # reference partials, plus the direction codes of at least one block
+    # (2 bits per cell, rows padded by 63) per query
+    assert ws >= 3 * 50000 * 4 + (lens.sum() + 63 * 3) * 1024 // 4
+    assert ws < 2 << 30
+    assert P.sdtw_backward_workspace_bytes(np.array([8192], np.int32), 100, 64) > 0
+    assert P.sdtw_backward_workspace_bytes(np.array([8193], np.int32), 100, 64) == 0
     assert P.sdtw_backward_workspace_bytes(lens, 50000, 0) == 0
+    assert P.sdtw_backward_workspace_bytes(lens, 50000, 24) == 0

@@ -49,11 +49,12 @@ def test_ragged_batch_matches_oracle_walk(kind, ckpt_every):
     _check_vs_oracle(w, g, kind, ckpt_every, f"kind {kind} K {ckpt_every}")
 
 
-@pytest.mark.parametrize("n", [1000, 1500, 2048])
-def test_longer_queries_fewer_waves(n):
-    """Queries beyond 512 / 1,024 rows run with 2 / 1 wavefronts per query."""
-    w = workloads.make_random(3, [n, n // 2, 7], 6000, seed=17 + n)
-    _check_vs_oracle(w, np.ones(3, np.float32), 0, 1024, f"n {n}")
+@pytest.mark.parametrize("n,ckpt_every", [(1000, 1024), (2048, 2048), (4100, 3072), (8192, 1024)])
+def test_long_queries_and_multi_segment_blocks(n, ckpt_every):
+    """Long queries (up to the 8,192-row limit of the backward) and blocks
+    wider than one 1,024-column recompute segment."""
+    w = workloads.make_random(3, [n, n // 2, 7], max(5000, n * 3 // 2), seed=17 + n)
+    _check_vs_oracle(w, np.ones(3, np.float32), 0, ckpt_every, f"n {n} K {ckpt_every}")
 
 
 def test_path_crossing_many_blocks():
