@@ -157,13 +157,15 @@ int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t 
   return best;
 }
 
-// Backward: direction codes of `slots` blocks per query are held at once
-// (one round); the code buffer is kept under kBwdCodeBudget bytes where the
-// batch allows, with at least one block per round.
-constexpr size_t kBwdCodeBudget = size_t(1) << 30;
+// Backward: direction codes of `slots` blocks per query are held per round,
+// in two buffers (the walk of one round overlaps the recompute of the next);
+// both are kept under kBwdCodeBudget bytes where the batch allows, with at
+// least one block per round.
+constexpr size_t kBwdCodeBudget = size_t(2) << 30;
 
 struct BwdLayout {
   size_t offsets, state, lo, row_lo, row_hi, part, codes, total;
+  int64_t code_half;          // words per code buffer
   int32_t nseg, slots, rounds;
 };
 
@@ -174,7 +176,7 @@ BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t 
       (size_t)L.nseg * sdtw::kWave * ((size_t)total_len + (size_t)(sdtw::kWave - 1) * batch);
   const size_t bytes_per_slot = words_per_slot * sizeof(uint32_t);
   const int64_t nblk = (ref_len + ckpt_every - 1) / ckpt_every;
-  int64_t slots = (int64_t)(kBwdCodeBudget / bytes_per_slot);
+  int64_t slots = (int64_t)(kBwdCodeBudget / (2 * bytes_per_slot));
   slots = std::max<int64_t>(1, std::min<int64_t>({slots, sdtw::kBwdMaxSlots, nblk}));
   L.slots = (int32_t)slots;
   L.rounds = (int32_t)((nblk + slots - 1) / slots);
@@ -192,7 +194,8 @@ BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t 
   L.part = at;
   at = align_up(at + sizeof(float) * (size_t)batch * (size_t)row_stride_floats(ref_len), kAlign);
   L.codes = at;
-  at = align_up(at + bytes_per_slot * (size_t)slots, kAlign);
+  L.code_half = (int64_t)(words_per_slot * (size_t)slots);
+  at = align_up(at + 2 * bytes_per_slot * (size_t)slots, kAlign);
   L.total = at;
   return L;
 }
@@ -393,6 +396,7 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
   p.slots = L.slots;
   p.max_rows = nmax;
   p.round = 0;
+  p.code_half = L.code_half;
 
   int rc;
   {
@@ -408,27 +412,37 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
                 dim3(sdtw::kInitThreads), args, stream);
     if (rc != SDTW_OK) return rc;
   }
-  const void* dirs = cost_kind == SDTW_COST_SQUARED
-                         ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
-                         : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
-  const size_t dirs_lds = sizeof(float) * 2 * (size_t)nmax;
+  const bool sq = cost_kind == SDTW_COST_SQUARED;
+  const size_t round_lds = sdtw::bwd_round_lds_bytes(nmax);
+  {
+    const void* dirs = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
+                          : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
+    void* args[] = {(void*)&p};
+    if (hipLaunchKernel(dirs, dim3(batch, L.slots), dim3(sdtw::kWave), args, round_lds,
+                        stream) != hipSuccess)
+      return SDTW_ERR_HIP;
+  }
+  const void* round_fn = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<0>)
+                            : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<1>);
   for (int r = 0; r < L.rounds; ++r) {
     p.round = r;
+    const int64_t grid = (int64_t)batch * (r + 1 < L.rounds ? 1 + L.slots : 1);
     void* args[] = {(void*)&p};
-    if (hipLaunchKernel(dirs, dim3(batch, L.slots), dim3(sdtw::kWave), args, dirs_lds, stream) !=
-        hipSuccess)
+    if (hipLaunchKernel(round_fn, dim3((unsigned)grid), dim3(sdtw::kWave), args, round_lds,
+                        stream) != hipSuccess)
       return SDTW_ERR_HIP;
-    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_bwd_walk_kernel), dim3(batch),
-                dim3(sdtw::kWave), args, stream);
-    if (rc != SDTW_OK) return rc;
   }
   {
-    const void* grad = cost_kind == SDTW_COST_SQUARED
-                           ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<0>)
-                           : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1>);
+    const bool qlds = sdtw::bwd_grad_q_in_lds(nmax);
+    const void* grad =
+        sq ? (qlds ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<0, true>)
+                   : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<0, false>))
+           : (qlds ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1, true>)
+                   : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1, false>));
     void* args[] = {(void*)&p};
-    rc = launch(grad, dim3(batch), dim3(sdtw::kGradThreads), args, stream);
-    if (rc != SDTW_OK) return rc;
+    if (hipLaunchKernel(grad, dim3(batch), dim3(sdtw::kGradThreads), args,
+                        sdtw::bwd_grad_lds_bytes(nmax), stream) != hipSuccess)
+      return SDTW_ERR_HIP;
   }
   {
     const float* part = p.ref_part;

@@ -47,10 +47,16 @@ constexpr int kDirMaxRows = 8192;               // query + left column held in L
 constexpr int kWalkChunk = 64;                  // code rows per walker LDS chunk
 constexpr int kBwdMaxSlots = 8;                 // blocks per round per query
 
-// Direction codes (2 bits per cell; cell c of a word at bits 2c, 2c+1).
-constexpr uint32_t kDirDiag = 0;
-constexpr uint32_t kDirUp = 1;
-constexpr uint32_t kDirLeft = 2;
+// Direction code of a cell, 2 bits (cell c of a word at bits 2c, 2c+1):
+// bit 0 = "the diagonal is not a minimum", bit 1 = "the cell above is not a
+// minimum".  The walk steps diagonally if bit 0 is clear, else up if bit 1 is
+// clear, else left (ties: diagonal, then up, then left).  DP values are
+// never negative (nor -0), so their bit patterns order like the values and
+// x != min is the unsigned difference of the patterns clamped to 1.
+__device__ __forceinline__ uint32_t not_min_bit(float x, float mn) {
+  const uint32_t d = __builtin_bit_cast(uint32_t, x) - __builtin_bit_cast(uint32_t, mn);
+  return d < 1u ? d : 1u;
+}
 
 struct BwdParams {
   const float* queries;       // packed
@@ -74,8 +80,9 @@ struct BwdParams {
   int32_t n_ckpt;
   int32_t nseg;               // segments per block, ceil(ckpt_every / kDirSeg)
   int32_t slots;              // blocks per round (G)
-  int32_t max_rows;           // longest query (sizes the dirs kernel's LDS)
+  int32_t max_rows;           // longest query (sizes the LDS of the kernels)
   int32_t round;
+  int64_t code_half;          // words of one code buffer (two alternate by round)
 };
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -87,14 +94,15 @@ __device__ __forceinline__ int64_t wave_uniform64(int64_t v) {
   return (int64_t)(((unsigned long long)hi << 32) | lo);
 }
 
-// Codes of segment s of round slot t of query b: n + 63 rows of 64 words;
-// word l of row g holds the 16 codes of lane l at step g, i.e. of query row
+// Codes of segment s of round slot t of query b in the code buffer of round
+// r (rounds alternate between two buffers): n + 63 rows of 64 words; word l
+// of row g holds the 16 codes of lane l at step g, i.e. of query row
 // i = g - l + 1 and columns 16l .. 16l+15 of the segment.
-__device__ __forceinline__ int64_t code_segment(const BwdParams& p, int b, int64_t qoff, int n,
-                                                int t, int s) {
+__device__ __forceinline__ int64_t code_segment(const BwdParams& p, int r, int b, int64_t qoff,
+                                                int n, int t, int s) {
   const int64_t rows = (int64_t)n + kWave - 1;
   const int64_t base = (int64_t)p.slots * p.nseg * kWave * (qoff + (int64_t)(kWave - 1) * b);
-  return base + ((int64_t)t * p.nseg + s) * rows * kWave;
+  return (r & 1) * p.code_half + base + ((int64_t)t * p.nseg + s) * rows * kWave;
 }
 
 // Local-cost derivative with respect to the query value at t = q - r.
@@ -140,8 +148,8 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, const floa
   for (int c = 0; c < kDirCols; ++c) {
     const float up = dprev[c];
     const float mn = min3(up, left, diag);
-    const uint32_t code = diag == mn ? kDirDiag : (up == mn ? kDirUp : kDirLeft);
-    word |= code << (2 * c);
+    word |= not_min_bit(diag, mn) << (2 * c);
+    word |= not_min_bit(up, mn) << (2 * c + 1);
     cur[c] = mn + local_cost<KIND>(qv, rv[c]);
     diag = up;
     left = cur[c];
@@ -159,20 +167,18 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, const floa
   shp = shc;
 }
 
-// Recompute rows 1..i of one block (i = the walker's current row) and store
-// its direction codes.  Grid: (batch, slots); one wavefront per workgroup.
-// Dynamic LDS: query values and the left boundary column, 2 * max_rows floats.
+// Recompute rows 1..i of block slot t of round r of query b (i = the
+// walker's current row as last stored; it only decreases, so any value read
+// is enough) and store its direction codes.  One wavefront; LDS `dyn`: query
+// values and the left boundary column, 2 * max_rows floats.
 template <int KIND>
-__global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p) {
-  extern __shared__ float dyn[];
-  const int b = blockIdx.x;
-  const int t = blockIdx.y;
+__device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int t, float* dyn) {
   const int lane = threadIdx.x;
   if (wave_uniform(p.state[4 * b + 2]) != 0) return;
   const int K = p.ckpt_every;
   const int64_t e = wave_uniform64(p.end_pos[b]);
   const int blk_end = (int)(e / K);
-  const int blk = blk_end - p.round * p.slots - t;
+  const int blk = blk_end - r * p.slots - t;
   if (blk < 0) return;
   const int n = wave_uniform(p.lens[b]);
   const int nrows = wave_uniform(p.state[4 * b + 0]);
@@ -199,7 +205,7 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p)
       const int j = cs + lane * kDirCols + c;
       rv[c] = j < bend ? p.reference[j] : 0.0f;
     }
-    uint32_t* out = p.codes + code_segment(p, b, qoff, n, t, s) + lane;
+    uint32_t* out = p.codes + code_segment(p, r, b, qoff, n, t, s) + lane;
     float dprev[kDirCols];
 #pragma unroll
     for (int c = 0; c < kDirCols; ++c) dprev[c] = 0.0f;      // row 0
@@ -209,6 +215,10 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p)
     int g = 0;
     for (; g < g_head; ++g)
       dirs_step<KIND, true>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+    for (; g + 1 < nrows; g += 2) {
+      dirs_step<KIND, false>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+      dirs_step<KIND, false>(g + 1, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+    }
     for (; g < nrows; ++g)
       dirs_step<KIND, false>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
     for (; g < g_end; ++g)
@@ -216,14 +226,36 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p)
   }
 }
 
-// Follow the direction codes of this round's blocks.  Grid: batch; one
-// wavefront per workgroup; every lane runs the same (uniform) walk and lane
-// 0 stores.  Code rows are staged through LDS 64 at a time: within a
-// segment the code row g = i - 1 + (lane owning column j) never increases
-// along the walk.
-__global__ __launch_bounds__(kWave) void sdtw_bwd_walk_kernel(const BwdParams p) {
-  __shared__ uint32_t chunk[kWalkChunk * kWave];
-  const int b = blockIdx.x;
+// Code rows [64k, 64k + 64) of a segment are 4096 consecutive words; each
+// lane holds 16 uint4 of them.  Rows past the segment's end read as zero
+// (they are never addressed).
+struct CodeChunk {
+  uint4 v[kWalkChunk * kWave / (4 * kWave)];
+
+  __device__ __forceinline__ void fetch(const uint32_t* seg, int k, int code_rows, int lane) {
+#pragma unroll
+    for (int u = 0; u < kWalkChunk / 4; ++u) {
+      const int e = 4 * (lane + kWave * u);             // word within the chunk
+      const int row = k * kWalkChunk + e / kWave;
+      v[u] = row < code_rows
+                 ? *reinterpret_cast<const uint4*>(seg + (int64_t)k * kWalkChunk * kWave + e)
+                 : make_uint4(0u, 0u, 0u, 0u);
+    }
+  }
+  __device__ __forceinline__ void commit(uint32_t* lds, int lane) const {
+#pragma unroll
+    for (int u = 0; u < kWalkChunk / 4; ++u)
+      *reinterpret_cast<uint4*>(lds + 4 * (lane + kWave * u)) = v[u];
+  }
+};
+
+// Follow the direction codes of round r's blocks of query b.  One wavefront;
+// every lane runs the same (uniform) walk and lane 0 stores.  Code rows are
+// staged through LDS (`chunk`, 64 rows) 64 at a time: within a segment the
+// code row g = i - 1 + (lane owning column j) never increases along the
+// walk, and falls by at most 2 per move, so the chunk below the current one
+// is always the next one needed and is fetched ahead.
+__device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uint32_t* chunk) {
   const int lane = threadIdx.x;
   if (wave_uniform(p.state[4 * b + 2]) != 0) return;
   int i = wave_uniform(p.state[4 * b + 0]);
@@ -238,34 +270,33 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_walk_kernel(const BwdParams p)
   int done = 0;
 
   for (int t = 0; t < p.slots && !done; ++t) {
-    const int blk = blk_end - p.round * p.slots - t;
+    const int blk = blk_end - r * p.slots - t;
     if (blk < 0) break;
     const int bc0 = blk * K;
     for (int s = (j - bc0) / kDirSeg; s >= 0 && !done; --s) {
       const int cs = bc0 + s * kDirSeg;
-      const uint32_t* seg = p.codes + code_segment(p, b, qoff, n, t, s);
-      int kc = -1;                              // code chunk held in LDS
+      const uint32_t* seg = p.codes + code_segment(p, r, b, qoff, n, t, s);
+      CodeChunk pre;                            // the chunk fetched ahead
+      int kc = -1, kp = -1;                     // chunk in LDS, chunk in `pre`
       while (j >= cs) {
         const int L = (j - cs) >> 4;
         const int c = (j - cs) & (kDirCols - 1);
         const int g = i - 1 + L;
         const int k = g / kWalkChunk;
         if (k != kc) {
-          // stage code rows [64k, 64k + 64); rows past the segment's end
-          // are never addressed
+          if (kp != k) pre.fetch(seg, k, code_rows, lane);
           __builtin_amdgcn_wave_barrier();
-          for (int m = 0; m < kWalkChunk; ++m) {
-            const int row = k * kWalkChunk + m;
-            if (row < code_rows) chunk[m * kWave + lane] = seg[(int64_t)row * kWave + lane];
-          }
+          pre.commit(chunk, lane);
           __builtin_amdgcn_wave_barrier();
           kc = k;
+          kp = k - 1;
+          if (k > 0) pre.fetch(seg, k - 1, code_rows, lane);
         }
         const uint32_t w =
             (uint32_t)wave_uniform((int)chunk[(g - k * kWalkChunk) * kWave + L]);
         // pass through the cells c, c-1, ... of this word whose code is
         // "left"; the first other one ends the run in this row
-        const uint32_t is_left = (w >> 1) & ~w & 0x55555555u;
+        const uint32_t is_left = (w >> 1) & w & 0x55555555u;
         const uint32_t upto = c == kDirCols - 1 ? 0xffffffffu : ((1u << (2 * c + 2)) - 1u);
         const uint32_t stop = ~is_left & 0x55555555u & upto;
         if (stop == 0) {
@@ -282,10 +313,10 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_walk_kernel(const BwdParams p)
           done = 1;
           break;
         }
-        const uint32_t code = (w >> bit) & 3u;
+        const bool diagonal = ((w >> bit) & 1u) == 0;
         if (lane == 0) rlo[i] = j;
         i -= 1;
-        if (code == kDirDiag) j -= 1;
+        if (diagonal) j -= 1;
         if (lane == 0) rhi[i] = j;
       }
     }
@@ -297,58 +328,134 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_walk_kernel(const BwdParams p)
   }
 }
 
-// Gradients from the recorded path rows.  Grid: batch; kGradThreads threads.
-//   grad_q[i]      = sum over the row's path columns j (descending) of g*dc/dq
-//   ref_part[b][j] = sum over the column's path rows i (descending) of -g*dc/dq
-// for j in [path_lo, end_pos].  Row i's columns are [row_lo[i], row_hi[i]];
-// both bounds are nondecreasing in i, so column j's rows are found by binary
-// search.
-constexpr int kGradThreads = 256;
+// Kernel LDS: the larger of the walker's code chunk and the dirs block's
+// query + left column.
+__host__ __device__ constexpr size_t bwd_round_lds_bytes(int max_rows) {
+  return sizeof(float) * 2 * (size_t)max_rows > sizeof(uint32_t) * kWalkChunk * kWave
+             ? sizeof(float) * 2 * (size_t)max_rows
+             : sizeof(uint32_t) * kWalkChunk * kWave;
+}
 
+// Round 0's blocks.  Grid: (batch, slots); one wavefront per workgroup.
 template <int KIND>
+__global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p) {
+  extern __shared__ __attribute__((aligned(16))) float dyn[];
+  dirs_block<KIND>(p, 0, blockIdx.x, blockIdx.y, dyn);
+}
+
+// Round r = p.round: workgroups [0, batch) walk round r; when another round
+// follows, workgroups [batch, batch + batch * slots) recompute round r+1's
+// blocks into the other code buffer meanwhile.  One wavefront per workgroup.
+template <int KIND>
+__global__ __launch_bounds__(kWave) void sdtw_bwd_round_kernel(const BwdParams p) {
+  extern __shared__ __attribute__((aligned(16))) float dyn[];
+  const int x = blockIdx.x;
+  if (x < p.batch) {
+    walk_query(p, p.round, x, reinterpret_cast<uint32_t*>(dyn));
+  } else {
+    const int k = x - p.batch;
+    dirs_block<KIND>(p, p.round + 1, k % p.batch, k / p.batch, dyn);
+  }
+}
+
+// Gradients from the recorded path rows.  Grid: batch; kGradThreads threads;
+// dynamic LDS: the row bounds (2 * max_rows ints) and, with QLDS, the query
+// values (max_rows floats).  Row i's path columns are [row_lo[i], row_hi[i]];
+// both bounds are nondecreasing in i, so the rows of column j are the run
+// from its top row (the first row with row_hi >= j) down to its bottom row
+// (the last row with row_lo <= j).
+//   grad_q[i]      = sum over row i's columns j (descending) of g*dc/dq,
+//                    one thread per row;
+//   ref_part[b][j] = sum over column j's rows i (descending) of -g*dc/dq,
+//                    for j in [path_lo, end_pos], each thread a contiguous
+//                    range of columns, following the top row along it.
+// Reference values are loaded in batches ahead of the sequential sums.
+constexpr int kGradThreads = 256;
+constexpr int kGradBatch = 8;                   // column sums
+constexpr int kGradRowBatch = 32;               // row sums (runs can be long)
+
+__host__ __device__ constexpr bool bwd_grad_q_in_lds(int max_rows) {
+  return sizeof(int32_t) * 3 * (size_t)max_rows <= 65536;
+}
+
+__host__ __device__ constexpr size_t bwd_grad_lds_bytes(int max_rows) {
+  return sizeof(int32_t) * (bwd_grad_q_in_lds(max_rows) ? 3 : 2) * (size_t)max_rows;
+}
+
+template <int KIND, bool QLDS>
 __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdParams p) {
+  extern __shared__ int32_t dyn_rows[];
   const int b = blockIdx.x;
+  const int tid = threadIdx.x;
   const int n = p.lens[b];
   const int64_t qoff = p.offsets[b];
-  const float* __restrict__ q = p.queries + qoff;
   const float* __restrict__ r = p.reference;
-  const int32_t* __restrict__ rlo = p.row_lo + qoff - 1;
-  const int32_t* __restrict__ rhi = p.row_hi + qoff - 1;
   const float gcost = p.grad_cost[b];
   float* __restrict__ gq = p.grad_q + qoff;
   float* __restrict__ part = p.ref_part + (int64_t)b * p.part_stride;
-
   // (the clamps only keep every access in bounds; a finished walk records
-  // every row, with columns in [0, end_pos])
+  // every row, with columns in [path_lo, end_pos])
   const int jhi = (int)p.end_pos[b];
-  for (int i = 1 + (int)threadIdx.x; i <= n; i += kGradThreads) {
+  const int jlo = p.path_lo[b] > 0 ? (p.path_lo[b] < jhi ? p.path_lo[b] : jhi) : 0;
+  int32_t* rlo = dyn_rows - 1;                  // indexed by 1-based row
+  int32_t* rhi = dyn_rows + p.max_rows - 1;
+  float* lq = reinterpret_cast<float*>(dyn_rows + 2 * p.max_rows);
+  for (int i = 1 + tid; i <= n; i += kGradThreads) {
+    const int lo = p.row_lo[qoff + i - 1];
+    const int hi = p.row_hi[qoff + i - 1];
+    rlo[i] = lo > jlo ? (lo < jhi ? lo : jhi) : jlo;
+    rhi[i] = hi > jlo ? (hi < jhi ? hi : jhi) : jlo;
+    if constexpr (QLDS) lq[i - 1] = p.queries[qoff + i - 1];
+  }
+  __syncthreads();
+  const float* __restrict__ q = QLDS ? lq : p.queries + qoff;
+
+  for (int i = 1 + tid; i <= n; i += kGradThreads) {
     const float qi = q[i - 1];
-    const int lo = rlo[i] > 0 ? rlo[i] : 0;
-    const int hi = rhi[i] < jhi ? rhi[i] : jhi;
+    const int lo = rlo[i];
     float acc = 0.0f;
-    for (int jj = hi; jj >= lo; --jj) acc = acc + gcost * dcost_dq<KIND>(qi, r[jj]);
+    int jj = rhi[i];
+    for (; jj - (kGradRowBatch - 1) >= lo; jj -= kGradRowBatch) {
+      float rv[kGradRowBatch];
+#pragma unroll
+      for (int u = 0; u < kGradRowBatch; ++u) rv[u] = r[jj - u];
+#pragma unroll
+      for (int u = 0; u < kGradRowBatch; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
+    }
+    for (; jj >= lo; --jj) acc = acc + gcost * dcost_dq<KIND>(qi, r[jj]);
     gq[i - 1] = acc;
   }
 
-  const int jlo = p.path_lo[b] > 0 ? p.path_lo[b] : 0;
-  for (int jj = jlo + (int)threadIdx.x; jj <= jhi; jj += kGradThreads) {
-    int a = 1, z = n;                           // first row whose last column reaches jj
+  const int span = jhi - jlo + 1;
+  const int per = (span + kGradThreads - 1) / kGradThreads;
+  const int j0 = jlo + tid * per;
+  const int j1 = j0 + per < jhi + 1 ? j0 + per : jhi + 1;
+  if (j0 < j1) {
+    int a = 1, z = n;                           // top row of column j0
     while (a < z) {
       const int mid = (a + z) >> 1;
-      if (rhi[mid] >= jj) z = mid; else a = mid + 1;
+      if (rhi[mid] >= j0) z = mid; else a = mid + 1;
     }
-    const int top = a;
-    z = n;                                      // last row whose first column is <= jj
-    while (a < z) {
-      const int mid = (a + z + 1) >> 1;
-      if (rlo[mid] <= jj) a = mid; else z = mid - 1;
+    int top = a;
+    float qtop = q[top - 1];
+    for (int jb = j0; jb < j1; jb += kGradBatch) {
+      float rv[kGradBatch];
+#pragma unroll
+      for (int u = 0; u < kGradBatch; ++u) rv[u] = jb + u < j1 ? r[jb + u] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < kGradBatch; ++u) {
+        const int jj = jb + u;
+        if (jj < j1) {
+          while (top < n && rhi[top] < jj) qtop = q[(++top) - 1];
+          int bottom = top;
+          while (bottom < n && rlo[bottom + 1] <= jj) ++bottom;
+          float acc = 0.0f;
+          for (int ii = bottom; ii > top; --ii)
+            acc = acc + (-(gcost * dcost_dq<KIND>(q[ii - 1], rv[u])));
+          part[jj] = acc + (-(gcost * dcost_dq<KIND>(qtop, rv[u])));
+        }
+      }
     }
-    const int bottom = a;
-    const float rj = r[jj];
-    float acc = 0.0f;
-    for (int ii = bottom; ii >= top; --ii)
-      acc = acc + (-(gcost * dcost_dq<KIND>(q[ii - 1], rj)));
-    part[jj] = acc;
   }
 }
 
