@@ -198,12 +198,18 @@ def fwd_bwd_leg(P, torch, steps, warmup):
     gq = torch.empty_like(q)
     gr = torch.empty_like(r)
 
+    # forward tile for this shape, timed without checkpoints (they add a few
+    # stores per K columns)
+    from paper_2403_06931_amd import autotune as A
+    rec = {}
+    var = A.tune(q, w.lens, l, r, 0, 0, reps=2, record=rec)
+
     def fwd():
         P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, ckpt=ckpt, ckpt_every=K,
-                       flags=flags, workspace_buf=ws)
+                       variant=var, flags=flags, workspace_buf=ws)
 
     def bwd():
-        P.sdtw_backward(q, w.lens, l, r, 0, g, end, ckpt, K, grad_queries=gq,
+        P.sdtw_backward(q, w.lens, l, r, 0, g, cost, end, ckpt, K, grad_queries=gq,
                         grad_reference=gr, workspace_buf=wsb)
 
     def both():
@@ -212,16 +218,16 @@ def fwd_bwd_leg(P, torch, steps, warmup):
     _, f_ms = time_steps(fwd, steps, warmup, torch)
     _, b_ms = time_steps(bwd, steps, warmup, torch)
     _, fb_ms = time_steps(both, steps, warmup, torch)
-    plain_var = P.sdtw_default_variant(w.lens, w.ref_len, 0)
 
     def plain():
-        P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, workspace_buf=ws)
+        P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, variant=var,
+                       workspace_buf=ws)
     _, p_ms = time_steps(plain, steps, warmup, torch)
     return {"workload": w.name, "cells": w.cells, "ckpt_every": K,
             "gcups": w.cells / (fb_ms * 1e6), "ms_per_step": fb_ms,
             "fwd_ckpt_ms": f_ms, "bwd_ms": b_ms, "plain_fwd_ms": p_ms,
             "plain_fwd_gcups": w.cells / (p_ms * 1e6),
-            "variant": P.sdtw_variant_info(plain_var)}
+            "variant": P.sdtw_variant_info(var), "tuned_over": len(rec.get("times_ms", {}))}
 
 
 def main():

@@ -165,6 +165,7 @@ SDTW_API size_t sdtw_backward_workspace_bytes(const int32_t *h_query_lens, int32
  *       no path touches.
  *
  *   grad_cost       device float32 [batch]
+ *   cost            device float32 [batch], as returned by sdtw_forward
  *   end_pos         device int64 [batch], as returned by sdtw_forward
  *   ckpt            device float32, as filled by sdtw_forward (may be NULL
  *                   when sdtw_checkpoint_floats(...) is 0)
@@ -177,7 +178,7 @@ SDTW_API size_t sdtw_backward_workspace_bytes(const int32_t *h_query_lens, int32
 SDTW_API int sdtw_backward(const float *queries, const int32_t *h_query_lens,
                   const int32_t *query_lens, int32_t batch,
                   const float *reference, int64_t ref_len, int32_t cost_kind,
-                  const float *grad_cost, const int64_t *end_pos,
+                  const float *grad_cost, const float *cost, const int64_t *end_pos,
                   const float *ckpt, int32_t ckpt_every,
                   float *grad_queries, float *grad_reference,
                   void *workspace, size_t workspace_bytes, void *stream);

@@ -58,7 +58,7 @@ def _load():
                                                   ctypes.c_int32]
     lib.sdtw_backward_workspace_bytes.restype = ctypes.c_size_t
     lib.sdtw_backward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
-                                  ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
+                                  ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
                                   _vp, ctypes.c_size_t, _vp]
     lib.sdtw_backward.restype = ctypes.c_int
     return lib

@@ -127,17 +127,20 @@ def sdtw_forward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
 
 def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
                   reference: torch.Tensor, cost_kind: int, grad_cost: torch.Tensor,
-                  end_pos: torch.Tensor, ckpt: Optional[torch.Tensor], ckpt_every: int, *,
+                  cost: torch.Tensor, end_pos: torch.Tensor, ckpt: Optional[torch.Tensor],
+                  ckpt_every: int, *,
                   grad_queries: Optional[torch.Tensor] = None,
                   grad_reference: Optional[torch.Tensor] = None,
                   workspace_buf: Optional[torch.Tensor] = None,
                   stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Walk-back gradient (grad_queries packed like queries, grad_reference [M])."""
+    """Walk-back gradient (grad_queries packed like queries, grad_reference [M]);
+    cost and end_pos are the forward's outputs."""
     h = _host_lens(h_query_lens)
     _require_cuda("queries", queries, torch.float32)
     _require_cuda("query_lens", query_lens, torch.int32)
     _require_cuda("reference", reference, torch.float32)
     _require_cuda("grad_cost", grad_cost, torch.float32)
+    _require_cuda("cost", cost, torch.float32)
     _require_cuda("end_pos", end_pos, torch.int64)
     dev = queries.device
     if grad_queries is None:
@@ -151,7 +154,7 @@ def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
         workspace_buf = workspace(need, dev)
     st = _lib.lib.sdtw_backward(
         _dp(queries), _hp(h), _dp(query_lens), h.size, _dp(reference), reference.numel(),
-        int(cost_kind), _dp(grad_cost), _dp(end_pos), _dp(ckpt), int(ckpt_every),
+        int(cost_kind), _dp(grad_cost), _dp(cost), _dp(end_pos), _dp(ckpt), int(ckpt_every),
         _dp(grad_queries), _dp(grad_reference), _dp(workspace_buf), workspace_buf.numel(),
         _stream(stream))
     check(st, "sdtw_backward")

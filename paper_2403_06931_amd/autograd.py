@@ -24,7 +24,7 @@ class SDTWFunction(torch.autograd.Function):
         cost, end = api.sdtw_forward(queries.detach(), h, query_lens, reference.detach(),
                                      cost_kind, ckpt=ckpt if nck else None,
                                      ckpt_every=ckpt_every, flags=api.SDTW_F_CHECKPOINT)
-        ctx.save_for_backward(queries, reference, query_lens, end, ckpt)
+        ctx.save_for_backward(queries, reference, query_lens, cost, end, ckpt)
         ctx.h_lens = h
         ctx.cost_kind = cost_kind
         ctx.ckpt_every = ckpt_every
@@ -34,12 +34,13 @@ class SDTWFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_cost, grad_end):
-        queries, reference, query_lens, end, ckpt = ctx.saved_tensors
+        queries, reference, query_lens, cost, end, ckpt = ctx.saved_tensors
         if grad_cost is None:
             return None, None, None, None, None, None
         g = grad_cost.detach().to(torch.float32).contiguous()
         gq, gr = api.sdtw_backward(queries.detach(), ctx.h_lens, query_lens, reference.detach(),
-                                   ctx.cost_kind, g, end, ckpt if ctx.has_ckpt else None,
+                                   ctx.cost_kind, g, cost, end,
+                                   ckpt if ctx.has_ckpt else None,
                                    ctx.ckpt_every)
         return gq, gr, None, None, None, None
 

@@ -349,13 +349,14 @@ size_t sdtw_backward_workspace_bytes(const int32_t* h_query_lens, int32_t batch,
 
 int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
                   int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
-                  const float* grad_cost, const int64_t* end_pos, const float* ckpt,
+                  const float* grad_cost, const float* cost, const int64_t* end_pos,
+                  const float* ckpt,
                   int32_t ckpt_every, float* grad_queries, float* grad_reference, void* workspace,
                   size_t workspace_bytes, void* stream_ptr) {
   int64_t total = 0;
   int32_t nmax = 0;
-  if (!queries || !query_lens || !reference || !grad_cost || !end_pos || !grad_queries ||
-      !grad_reference || !workspace)
+  if (!queries || !query_lens || !reference || !grad_cost || !cost || !end_pos ||
+      !grad_queries || !grad_reference || !workspace)
     return SDTW_ERR_INVALID_ARG;
   if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
     return SDTW_ERR_INVALID_ARG;
@@ -378,6 +379,7 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
   p.offsets = offs;
   p.reference = reference;
   p.grad_cost = grad_cost;
+  p.cost = cost;
   p.end_pos = end_pos;
   p.ckpt = ckpt;
   p.grad_q = grad_queries;

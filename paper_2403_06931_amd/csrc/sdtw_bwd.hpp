@@ -64,6 +64,7 @@ struct BwdParams {
   const int64_t* offsets;     // [batch + 1]
   const float* reference;     // [ref_len]
   const float* grad_cost;     // [batch]
+  const float* cost;          // [batch], the forward's
   const int64_t* end_pos;     // [batch]
   const float* ckpt;          // forward checkpoints (nullptr when n_ckpt == 0)
   float* grad_q;              // packed like queries
@@ -168,8 +169,9 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, const floa
 }
 
 // Recompute rows 1..i of block slot t of round r of query b (i = the
-// walker's current row as last stored; it only decreases, so any value read
-// is enough) and store its direction codes.  One wavefront; LDS `dyn`: query
+// walker's current row as last stored, which only decreases, so any value
+// read is enough; lowered further by the block's right checkpoint column)
+// and store its direction codes.  One wavefront; LDS `dyn`: query
 // values and the left boundary column, 2 * max_rows floats.
 template <int KIND>
 __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int t, float* dyn) {
@@ -181,8 +183,24 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
   const int blk = blk_end - r * p.slots - t;
   if (blk < 0) return;
   const int n = wave_uniform(p.lens[b]);
-  const int nrows = wave_uniform(p.state[4 * b + 0]);
+  int nrows = wave_uniform(p.state[4 * b + 0]);
   const int64_t qoff = wave_uniform64(p.offsets[b]);
+  if (blk < blk_end) {
+    // D never decreases along the path, so the cell where the walk enters
+    // this block (in its last column, which checkpoint blk+1 holds) has
+    // D <= cost: rows below the last such row are not needed.
+    const float* ckr = p.ckpt + qoff * p.n_ckpt + (int64_t)blk * n;
+    const float cost = p.cost[b];
+    int last = 0;
+    for (int k = lane; k < nrows; k += kWave)
+      if (ckr[k] <= cost) last = k + 1;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      const int o = __shfl_xor(last, off);
+      last = o > last ? o : last;
+    }
+    nrows = wave_uniform(last);
+    if (nrows == 0) return;                    // the path does not reach this block
+  }
   float* lq = dyn;
   float* ledge = dyn + p.max_rows;
   const float* __restrict__ q = p.queries + qoff;

@@ -115,17 +115,17 @@ def test_workspace_sizes(L):
 
 def _bwd(L, lens, ref_len=100, kind=0, every=64, ckpt=FAKE, ws_bytes=1 << 40, **ptrs):
     h = np.ascontiguousarray(lens, dtype=np.int32)
-    a = dict(q=FAKE, dlens=FAKE, r=FAKE, g=FAKE, e=FAKE, gq=FAKE, gr=FAKE, ws=FAKE)
+    a = dict(q=FAKE, dlens=FAKE, r=FAKE, g=FAKE, c=FAKE, e=FAKE, gq=FAKE, gr=FAKE, ws=FAKE)
     a.update(ptrs)
     return L.lib.sdtw_backward(_vp(a["q"]), _vp(h.ctypes.data), _vp(a["dlens"]), h.size,
-                               _vp(a["r"]), ref_len, kind, _vp(a["g"]), _vp(a["e"]),
+                               _vp(a["r"]), ref_len, kind, _vp(a["g"]), _vp(a["c"]), _vp(a["e"]),
                                _vp(ckpt), every, _vp(a["gq"]), _vp(a["gr"]), _vp(a["ws"]),
                                ws_bytes, _vp(0))
 
 
 def test_backward_rejects_invalid_arguments(L):
     E = L.SDTW_ERR_INVALID_ARG
-    for name in ("q", "dlens", "r", "g", "e", "gq", "gr", "ws"):
+    for name in ("q", "dlens", "r", "g", "c", "e", "gq", "gr", "ws"):
         assert _bwd(L, [3, 4], **{name: 0}) == E, name
     assert _bwd(L, [3, 0]) == E
     assert _bwd(L, [3, 4], kind=5) == E

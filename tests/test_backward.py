@@ -23,7 +23,8 @@ def _gpu_grad(w, g, kind=0, ckpt_every=256):
     cost, end = P.sdtw_forward(q, w.lens, l, r, kind, ckpt=ckpt if nck else None,
                                ckpt_every=ckpt_every, flags=P.SDTW_F_CHECKPOINT)
     gc = torch.from_numpy(np.asarray(g, np.float32)).to(q.device)
-    gq, gr = P.sdtw_backward(q, w.lens, l, r, kind, gc, end, ckpt if nck else None, ckpt_every)
+    gq, gr = P.sdtw_backward(q, w.lens, l, r, kind, gc, cost, end, ckpt if nck else None,
+                             ckpt_every)
     torch.cuda.synchronize()
     return (cost.cpu().numpy(), end.cpu().numpy(), gq.cpu().numpy(), gr.cpu().numpy())
 
