@@ -43,14 +43,19 @@ def valu_peak_gcups(ops_per_cell, cus=PEAK_CUS, ghz=PEAK_GHZ, lanes=LANES_PER_CU
     return cus * lanes * ghz / ops_per_cell   # G lane-instr/s / instr per cell
 
 
+# Sources that define the forward kernel's code (its arithmetic, memory
+# traffic and compile flags); counter summaries are tied to their digest.
+FWD_SOURCES = ("sdtw_common.hpp", "sdtw_argmin.hpp", "sdtw_fwd.hpp", "sdtw_variant.hpp",
+               "sdtw_variant_tu.hip", "build.py")
+
+
 def source_digest():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2403_06931_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hpp", ".hip", ".inc")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in FWD_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
