@@ -137,7 +137,9 @@ struct LaneState {
   float bot[T];    // the lane's bottom row over the last tile (feeds lane + 1)
   float corner;    // top boundary at the column before the current tile
   int ck_cnt;      // steps until the next checkpoint column
-  int ck_idx;      // next checkpoint index
+  int ck_idx;      // index of the next checkpoint to store
+  bool ck_pend;    // ckv holds a checkpoint column not yet stored
+  float ckv[R];    // the lane's rows at the last checkpoint column reached
 };
 
 // Uniform (per wavefront) geometry of one pass.
@@ -146,9 +148,28 @@ struct PassGeom {
   int my_delay, lane0_delay, lane63_delay;   // tile = step - delay
   int out_delay, out_lane;                   // lane holding the row to store
   int tiles_per_ckpt;
+  bool ck_each_step;                         // store checkpoints every step
   int64_t qoff;
   float* row;                                // row-buffer slot of the query
 };
+
+// Store a captured checkpoint column.  Called once per barrier interval,
+// or every step when checkpoints come closer than one interval apart, so a
+// lane never captures twice before storing.
+template <int R, int T>
+__device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& L,
+                                           const PassGeom& G) {
+  if (L.ck_pend) {
+    if (L.ck_idx < p.n_ckpt) {
+      float* dst = p.ckpt + G.qoff * p.n_ckpt + (int64_t)L.ck_idx * G.n + G.row0;
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        if (G.row0 + k < G.n) dst[k] = L.ckv[k];
+    }
+    ++L.ck_idx;
+    L.ck_pend = false;
+  }
+}
 
 // One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
 // the wavefront holding the row to store and that row's register index.
@@ -205,17 +226,16 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
 
   if constexpr (CKPT) {
     // Checkpoint column kc*ckpt_every - 1 is the last column of a tile
-    // (ckpt_every is a multiple of T); a per-lane countdown finds it.
-    if (--L.ck_cnt == 0) {
-      L.ck_cnt = G.tiles_per_ckpt;
-      if (L.ck_idx < p.n_ckpt) {
-        float* dst = p.ckpt + G.qoff * p.n_ckpt + (int64_t)L.ck_idx * G.n + G.row0;
+    // (ckpt_every is a multiple of T); a per-lane countdown finds it.  The
+    // lane's rows there are captured with selects and stored once per
+    // barrier interval (lanes reach the column on different steps).
+    --L.ck_cnt;
+    const bool hit = L.ck_cnt == 0;
+    L.ck_cnt = hit ? G.tiles_per_ckpt : L.ck_cnt;
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-          if (G.row0 + k < G.n) dst[k] = L.dl[k];
-      }
-      ++L.ck_idx;
-    }
+    for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
+    L.ck_pend = L.ck_pend || hit;
+    if (G.ck_each_step) ckpt_flush(p, L, G);
   }
 }
 
@@ -255,6 +275,7 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
       step_inputs<R, T, W, KS>(rvA, injA, g + 2, G, s_ref, s_hand);
       fwd_step<R, T, W, KS, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand);
     }
+    if constexpr (CKPT) ckpt_flush(p, L, G);
     st.commit(s_ref, s_hand, (it + 2) * KS, tid);
     __syncthreads();
   }
@@ -298,6 +319,7 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   G.lane0_delay = G.wave * (kWave + S::LAG);
   G.lane63_delay = G.lane0_delay + kWave - 1;
   G.tiles_per_ckpt = CKPT ? p.ckpt_every / T : 1;
+  G.ck_each_step = G.tiles_per_ckpt < KS;
 
   for (int pass = 0; pass < npass; ++pass) {
     const int prow0 = pass * S::ROWS;                  // first row of this pass
@@ -313,6 +335,9 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     L.corner = inf_f32();
     L.ck_cnt = G.tiles_per_ckpt + G.my_delay;          // steps until tau = tiles_per_ckpt-1
     L.ck_idx = 0;
+    L.ck_pend = false;
+#pragma unroll
+    for (int k = 0; k < R; ++k) L.ckv[k] = 0.0f;
 
     // Row written to the row buffer by this pass: the pass's last row, or
     // row N on the final pass.
