@@ -291,7 +291,7 @@ def main():
     value = cells / (wall_ms * 1e6)
     achieved = cells / (ev_ms * 1e6)          # one kernel launch per step at this batch size
     peak = valu_peak_gcups(4)
-    R, T, W, KS = P.sdtw_variant_info(variant)
+    R, T, W, KS, XL = P.sdtw_variant_info(variant)
     gc = cost.cpu().numpy()
     ge = end.cpu().numpy()
     kernel_tag = "sdtw_fwd_512x2000_vs_100k"
@@ -311,11 +311,12 @@ def main():
         "config": {"workload": w.name, "queries": w.batch, "query_len": 2000,
                    "ref_len": w.ref_len, "cost": "squared", "cells": cells,
                    "variant": {"rows_per_lane": R, "tile_cols": T, "waves": W,
-                               "steps_per_barrier": KS},
+                               "steps_per_barrier": KS,
+                               "lane_exchange": "lds" if XL else "dpp"},
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "GCUPS",
                      "frac": achieved / peak, "traffic": measured_traffic(kernel_tag),
-                     "kernel": f"sdtw_fwd_kernel<{R},{T},{W},{KS},squared>",
+                     "kernel": f"sdtw_fwd_kernel<{R},{T},{W},{KS},{XL},squared>",
                      "kernel_ms": ev_ms,
                      "peak_basis": "256 CU x 128 lanes/clk (VALU dual issue) x 2.4 GHz / "
                                    "4 VALU ops per cell",

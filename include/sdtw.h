@@ -188,11 +188,13 @@ SDTW_API int32_t sdtw_variant_count(void);
 
 /*
  * Describe variant v: query rows held per lane, reference columns per step,
- * wavefronts per query, steps between workgroup barriers.  Any output pointer
- * may be NULL.  Returns SDTW_OK or SDTW_ERR_UNSUPPORTED.
+ * wavefronts per query, steps between workgroup barriers, and how a lane's
+ * bottom row reaches the next lane (1: through LDS, 0: DPP lane shift).  Any
+ * output pointer may be NULL.  Returns SDTW_OK or SDTW_ERR_UNSUPPORTED.
  */
 SDTW_API int sdtw_variant_info(int32_t v, int32_t *rows_per_lane, int32_t *tile_cols,
-                               int32_t *waves, int32_t *steps_per_barrier);
+                               int32_t *waves, int32_t *steps_per_barrier,
+                               int32_t *lane_exchange);
 
 /* Variant the library picks for this batch when variant = -1. */
 SDTW_API int32_t sdtw_default_variant(const int32_t *h_query_lens, int32_t batch,

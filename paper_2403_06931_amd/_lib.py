@@ -41,7 +41,8 @@ def _load():
     lib.sdtw_status_string.restype = ctypes.c_char_p
     lib.sdtw_variant_count.argtypes = []
     lib.sdtw_variant_count.restype = ctypes.c_int32
-    lib.sdtw_variant_info.argtypes = [ctypes.c_int32, _c_i32p, _c_i32p, _c_i32p, _c_i32p]
+    lib.sdtw_variant_info.argtypes = [ctypes.c_int32, _c_i32p, _c_i32p, _c_i32p, _c_i32p,
+                                      _c_i32p]
     lib.sdtw_variant_info.restype = ctypes.c_int
     lib.sdtw_default_variant.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.sdtw_default_variant.restype = ctypes.c_int32

@@ -65,12 +65,13 @@ def sdtw_variant_count() -> int:
     return int(_lib.lib.sdtw_variant_count())
 
 
-def sdtw_variant_info(v: int) -> Tuple[int, int, int, int]:
-    """(rows per lane, columns per step, wavefronts per query, steps per barrier)."""
-    r, t, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+def sdtw_variant_info(v: int) -> Tuple[int, int, int, int, int]:
+    """(rows per lane, columns per step, wavefronts per query, steps per barrier,
+    lane exchange: 1 through LDS, 0 DPP lane shift)."""
+    r, t, w, k, x = (ctypes.c_int32() for _ in range(5))
     check(_lib.lib.sdtw_variant_info(int(v), ctypes.byref(r), ctypes.byref(t), ctypes.byref(w),
-                                     ctypes.byref(k)), "sdtw_variant_info")
-    return r.value, t.value, w.value, k.value
+                                     ctypes.byref(k), ctypes.byref(x)), "sdtw_variant_info")
+    return r.value, t.value, w.value, k.value, x.value
 
 
 def sdtw_default_variant(h_query_lens, ref_len: int, flags: int = 0) -> int:

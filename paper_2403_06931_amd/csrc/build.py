@@ -31,10 +31,10 @@ FLAGS = [
 
 
 def variants():
-    """(index, R, T, W, KS) entries of the X-macro list in sdtw_variants.inc."""
+    """(index, R, T, W, KS, XL) entries of the X-macro list in sdtw_variants.inc."""
     text = open(VARIANT_LIST).read()
     return [tuple(int(x) for x in m.groups())
-            for m in re.finditer(r"X\((\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", text)]
+            for m in re.finditer(r"X\((\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", text)]
 
 
 # hipcc's host pass does not know the packed-fp32 feature and says so
@@ -56,10 +56,10 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile every translation unit (in parallel) and link libsdtw.so."""
     os.makedirs(OBJ_DIR, exist_ok=True)
     units = [(API_SOURCE, os.path.join(OBJ_DIR, "sdtw_api.o"), [])]
-    for i, r, t, w, ks in variants():
+    for i, r, t, w, ks, xl in variants():
         units.append((VARIANT_SOURCE, os.path.join(OBJ_DIR, f"sdtw_variant_{i}.o"),
                       [f"-DSDTW_VARIANT_INDEX={i}", f"-DSDTW_R={r}", f"-DSDTW_T={t}",
-                       f"-DSDTW_W={w}", f"-DSDTW_KS={ks}"]))
+                       f"-DSDTW_W={w}", f"-DSDTW_KS={ks}", f"-DSDTW_XL={xl}"]))
     jobs = jobs or min(len(units), max(1, min(16, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         futs = [ex.submit(_run, [HIPCC, *FLAGS, *defs, "-c", src, "-o", obj], verbose)

@@ -29,14 +29,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 using sdtw::Variant;
 
 const Variant& variant(int i) {
-#define SDTW_VARIANT_ENTRY(i, R, T, W, KS) sdtw_variant_entry_##i(),
+#define SDTW_VARIANT_ENTRY(i, R, T, W, KS, XL) sdtw_variant_entry_##i(),
   static const Variant table[] = {SDTW_VARIANTS(SDTW_VARIANT_ENTRY)};
 #undef SDTW_VARIANT_ENTRY
   return table[i];
 }
 
 int variant_count() {
-#define SDTW_COUNT_ONE(i, R, T, W, KS) +1
+#define SDTW_COUNT_ONE(i, R, T, W, KS, XL) +1
   return 0 SDTW_VARIANTS(SDTW_COUNT_ONE);
 #undef SDTW_COUNT_ONE
 }
@@ -107,16 +107,23 @@ double variant_cost(const Variant& v, const int32_t* h_lens, int32_t batch, int6
                     int cus) {
   const int64_t rows = 64LL * v.R * v.W;
   const int64_t ntiles = (ref_len + v.T - 1) / v.T;
-  const int64_t skew = 64LL * v.W - 1 + (v.W - 1) * (v.KS - 1);
+  const int64_t lane_lag = v.XL ? 2 : 1;
+  const int64_t skew = lane_lag * (64LL * v.W - 1) + (v.W - 1) * v.KS;
   double cells = 0;
   for (int32_t b = 0; b < batch; ++b) {
     const int64_t passes = (h_lens[b] + rows - 1) / rows;
     cells += (double)passes * rows * (double)(ntiles + skew) * v.T;
   }
-  // per-cell VALU work: 4 cell ops, one DPP move per row-block column, and
-  // about 8 per-step instructions
-  const double per_cell = 4.0 + 1.0 / v.R + 8.0 / (v.R * v.T);
-  const double wps = (double)batch * v.W / (4.0 * cus);          // wavefronts per SIMD
+  // per-cell VALU work: 4 cell ops and about 8 per-step instructions; the
+  // DPP form adds one move per row-block column, and its DPP moves cost
+  // dual issue (about 10 % measured at R = 8)
+  const double per_cell =
+      (4.0 + 8.0 / (v.R * v.T) + (v.XL ? 0.0 : 1.0 / v.R)) * (v.XL ? 1.0 : 1.1);
+  // wavefronts per SIMD: the batch's, capped by the workgroups one CU holds
+  // (160 KiB of LDS, 32 wavefronts)
+  constexpr int kLdsPerCu = 160 * 1024;
+  const int wg_per_cu = std::max(1, std::min(kLdsPerCu / std::max(1, v.lds_bytes), 32 / v.W));
+  const double wps = std::min((double)batch * v.W / (4.0 * cus), wg_per_cu * v.W / 4.0);
   static const double kIssue[] = {0.0, 0.55, 0.75, 0.85, 1.0};   // by min(4, ceil(wps))
   const int slot = wps <= 0 ? 1 : (wps >= 4 ? 4 : (int)(wps + 0.999));
   const double rate = kIssue[slot] * std::min(1.0, wps / slot);
@@ -225,13 +232,14 @@ const char* sdtw_status_string(int status) {
 int32_t sdtw_variant_count(void) { return variant_count(); }
 
 int sdtw_variant_info(int32_t v, int32_t* rows_per_lane, int32_t* tile_cols, int32_t* waves,
-                      int32_t* steps_per_barrier) {
+                      int32_t* steps_per_barrier, int32_t* lane_exchange) {
   if (v < 0 || v >= variant_count()) return SDTW_ERR_UNSUPPORTED;
   const Variant& x = variant(v);
   if (rows_per_lane) *rows_per_lane = x.R;
   if (tile_cols) *tile_cols = x.T;
   if (waves) *waves = x.W;
   if (steps_per_barrier) *steps_per_barrier = x.KS;
+  if (lane_exchange) *lane_exchange = x.XL;
   return SDTW_OK;
 }
 

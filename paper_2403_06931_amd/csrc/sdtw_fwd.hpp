@@ -8,15 +8,20 @@
 //     current column in registers;
 //   * the reference is streamed in tiles of T columns: at global step g a lane
 //     whose team position is L = 64*w + l computes the R x T block of tile
-//     tau = g - L - w*LAG;
+//     tau = g - 2L - w*LAG;
 //   * the DP values of a lane's bottom row for the T columns of a tile feed the
-//     next lane one step later through a DPP wave_shr:1 move (the paper's
-//     lane shuffle, Section 5.2);
+//     next lane through a per-lane LDS slot (the paper's lane shuffle, Section
+//     5.2).  Lanes lag their neighbour by two steps, so the slot written at the
+//     end of step g is read, one step ahead, during step g+1 and the LDS
+//     latency hides behind a step of arithmetic.  (A DPP lane shift is the
+//     obvious alternative; on gfx950 its DPP moves keep the SIMD from
+//     dual-issuing and measured about 20 % slower.)
 //   * lane 63 of wave w hands its bottom row to lane 0 of wave w+1 through an
 //     LDS ring (the paper's shared-memory handoff between consecutive
-//     wavefronts); the workgroup synchronises once every KSTEP steps and each
-//     wave lags the previous one by an extra LAG = KSTEP-1 steps so that every
-//     handoff crosses exactly one barrier;
+//     wavefronts); lane 0 reads it with the same load that reads the other
+//     lanes' slots.  The workgroup synchronises once every KSTEP steps and
+//     each wave lags the previous one by an extra LAG = KSTEP steps so that
+//     every handoff crosses a barrier;
 //   * reference tiles are staged from HBM into an LDS ring by the whole team,
 //     one interval ahead;
 //   * queries longer than 64*R*W rows are processed in passes; the last row of
@@ -58,31 +63,35 @@ struct FwdParams {
 
 constexpr int kStepsPerBarrier = 8;
 
-template <int R, int T, int W, int KS = kStepsPerBarrier>
+template <int R, int T, int W, int KS, int XL>
 struct FwdShape {
   static_assert(KS % 2 == 0, "the step loop is unrolled by two");
   static constexpr int KSTEP = KS;
+  // lane -> lane exchange: XL = 1 through LDS slots (lane l+1 lags lane l by
+  // two steps), XL = 0 through a DPP wave_shr:1 move (one step)
+  static constexpr int LL = XL ? 2 : 1;
   // Extra lag of wave w+1 behind wave w.  Data a wave hands over at step p is
-  // read (one step early, by the prefetch) at step p + KS, always in the next
-  // barrier interval.
+  // read (one step early, by the prefetch) at step p + KS + 1, always in a
+  // later barrier interval.
   static constexpr int LAG = KS;
   static constexpr int SH = 4 * KS;                           // handoff rings, tiles
   // reference tiles in flight: the oldest lane's tile up to the tiles staged
   // two intervals ahead
-  static constexpr int SPAN = kWave * W + (W - 1) * LAG + 3 * KS + 2;
+  static constexpr int SPAN = LL * kWave * W + (W - 1) * LAG + 3 * KS + 2;
   static constexpr int SR = pow2_ceil<SPAN>();                // reference ring, tiles
   static constexpr int THREADS = kWave * W;
   static constexpr int ROWS = kWave * R * W;                  // rows per pass
   static constexpr int CHUNK = KS * T;                        // floats staged per interval
-  static constexpr int LDS_FLOATS = SR * T + W * SH * T;
+  static constexpr int SLOTS = XL ? W * kWave * T : 0;        // lane -> lane slots
+  static constexpr int LDS_FLOATS = SR * T + W * SH * T + SLOTS;
 };
 
 // Stage the reference tiles [tile0, tile0 + KS) and the wave-0 top boundary
 // (zeros on the first pass, the previous pass's last row after it) from
 // global memory into registers; commit them to the LDS rings later.
-template <int R, int T, int W, int KS>
+template <int R, int T, int W, int KS, int XL>
 struct Stager {
-  using S = FwdShape<R, T, W, KS>;
+  using S = FwdShape<R, T, W, KS, XL>;
   static constexpr int PER = (S::CHUNK + S::THREADS - 1) / S::THREADS;
   float ref[PER];
   float top[PER];
@@ -173,16 +182,17 @@ __device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& 
 
 // One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
 // the wavefront holding the row to store and that row's register index.
-template <int R, int T, int W, int KS, int KIND, bool CKPT, int OUTK>
+// `top` is the block's top boundary: the previous lane's bottom row over this
+// tile (for lane 0, the previous wave's, or the top boundary of the pass).
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK>
 __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
                                          const PassGeom& G, const float (&rv)[T],
-                                         const float (&inj)[T], int g, float* s_hand) {
-  using S = FwdShape<R, T, W, KS>;
-  // top boundary: the previous lane's bottom row (DPP), for lane 0 the
-  // handoff ring of this wave
+                                         const float (&top)[T], int g, float* s_hand,
+                                         float* s_slot) {
+  using S = FwdShape<R, T, W, KS, XL>;
   float up[T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) up[t] = wave_shr1(inj[t], L.bot[t]);
+  for (int t = 0; t < T; ++t) up[t] = XL ? top[t] : wave_shr1(top[t], L.bot[t]);
   float upleft = L.corner;                      // D(row-1, first col - 1)
   L.corner = up[T - 1];
   const int tau_out = g - G.out_delay;
@@ -217,6 +227,14 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
 #pragma unroll
   for (int t = 0; t < T; ++t) L.bot[t] = up[t];
 
+  if constexpr (XL) {
+    // the bottom row feeds lane l+1 (its slot is read during the next step,
+    // before this lane overwrites it at the end of that step)
+    float* sout = s_slot + (G.wave * kWave + G.lane) * T;
+#pragma unroll
+    for (int t = 0; t < T; ++t) sout[t] = L.bot[t];
+  }
+
   // lane 63 hands its bottom row to the next wave
   if (G.wave + 1 < W && G.lane == kWave - 1) {
     float* hout = s_hand + (G.wave + 1) * S::SH * T + ((g - G.lane63_delay) & (S::SH - 1)) * T;
@@ -239,41 +257,44 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
   }
 }
 
-// LDS inputs of step g: this lane's reference tile and this wave's top
-// boundary (used by lane 0 only; every lane reads the same address).
-template <int R, int T, int W, int KS>
-__device__ __forceinline__ void step_inputs(float (&rv)[T], float (&inj)[T], int g,
+// LDS inputs of step g: this lane's reference tile and its top boundary
+// (lane 0: this wave's handoff ring; with XL the others read lane l-1's
+// slot, written at the end of step g-2; without, every lane reads the ring
+// and fwd_step shifts the bottom rows instead).
+template <int R, int T, int W, int KS, int XL>
+__device__ __forceinline__ void step_inputs(float (&rv)[T], float (&top)[T], int g,
                                             const PassGeom& G, const float* s_ref,
-                                            const float* s_hand) {
-  using S = FwdShape<R, T, W, KS>;
+                                            const float* s_hand, const float* s_slot) {
+  using S = FwdShape<R, T, W, KS, XL>;
   const float* rin = s_ref + ((g - G.my_delay) & (S::SR - 1)) * T;
   const float* hin = s_hand + G.wave * S::SH * T + ((g - G.lane0_delay) & (S::SH - 1)) * T;
+  const float* tin = (XL && G.lane != 0) ? s_slot + (G.wave * kWave + G.lane - 1) * T : hin;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     rv[t] = rin[t];
-    inj[t] = hin[t];
+    top[t] = tin[t];
   }
 }
 
 // All barrier intervals of one pass.  The LDS inputs of step g+1 are read
 // while step g computes (two register sets, the step loop unrolled by two).
-template <int R, int T, int W, int KS, int KIND, bool CKPT, int OUTK>
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK>
 __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
                                          const PassGeom& G, const float* prev_row,
-                                         float* s_ref, float* s_hand) {
+                                         float* s_ref, float* s_hand, float* s_slot) {
   const int tid = threadIdx.x;
   float rvA[T], injA[T], rvB[T], injB[T];
-  step_inputs<R, T, W, KS>(rvA, injA, 0, G, s_ref, s_hand);
+  step_inputs<R, T, W, KS, XL>(rvA, injA, 0, G, s_ref, s_hand, s_slot);
   for (int it = 0; it < G.nint; ++it) {
-    Stager<R, T, W, KS> st;
+    Stager<R, T, W, KS, XL> st;
     st.load(p.reference, p.ref_len, prev_row, G.ntiles * T, (it + 2) * KS, tid);
 #pragma unroll 1
     for (int s = 0; s < KS; s += 2) {
       const int g = it * KS + s;
-      step_inputs<R, T, W, KS>(rvB, injB, g + 1, G, s_ref, s_hand);
-      fwd_step<R, T, W, KS, KIND, CKPT, OUTK>(p, L, G, rvA, injA, g, s_hand);
-      step_inputs<R, T, W, KS>(rvA, injA, g + 2, G, s_ref, s_hand);
-      fwd_step<R, T, W, KS, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand);
+      step_inputs<R, T, W, KS, XL>(rvB, injB, g + 1, G, s_ref, s_hand, s_slot);
+      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK>(p, L, G, rvA, injA, g, s_hand, s_slot);
+      step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
+      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
     }
     if constexpr (CKPT) ckpt_flush(p, L, G);
     st.commit(s_ref, s_hand, (it + 2) * KS, tid);
@@ -283,25 +304,27 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
 
 // The wavefront holding the stored row runs a copy of the pass with that
 // row's register index as a compile-time constant; the others store nothing.
-template <int K, int R, int T, int W, int KS, int KIND, bool CKPT>
+template <int K, int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __device__ __forceinline__ void fwd_pass_out(int out_k, const FwdParams& p, LaneState<R, T>& L,
                                              const PassGeom& G, const float* prev_row,
-                                             float* s_ref, float* s_hand) {
+                                             float* s_ref, float* s_hand, float* s_slot) {
   if constexpr (K < R) {
     if (out_k == K) {
-      fwd_pass<R, T, W, KS, KIND, CKPT, K>(p, L, G, prev_row, s_ref, s_hand);
+      fwd_pass<R, T, W, KS, XL, KIND, CKPT, K>(p, L, G, prev_row, s_ref, s_hand, s_slot);
     } else {
-      fwd_pass_out<K + 1, R, T, W, KS, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand);
+      fwd_pass_out<K + 1, R, T, W, KS, XL, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand,
+                                                   s_slot);
     }
   }
 }
 
 // Process every pass of query b with the team of W waves of this workgroup.
 // `row` is this query's row-buffer slot.
-template <int R, int T, int W, int KS, int KIND, bool CKPT>
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qoff,
-                                          float* __restrict__ row, float* s_ref, float* s_hand) {
-  using S = FwdShape<R, T, W, KS>;
+                                          float* __restrict__ row, float* s_ref, float* s_hand,
+                                          float* s_slot) {
+  using S = FwdShape<R, T, W, KS, XL>;
   const int tid = threadIdx.x;
   PassGeom G;
   G.lane = tid & (kWave - 1);
@@ -313,11 +336,11 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   const float* __restrict__ q = p.queries + qoff;
   G.ntiles = (p.ref_len + T - 1) / T;
   const int npass = (G.n + S::ROWS - 1) / S::ROWS;
-  const int steps = G.ntiles + kWave * W - 1 + (W - 1) * S::LAG;
+  const int steps = G.ntiles + S::LL * (kWave * W - 1) + (W - 1) * S::LAG;
   G.nint = (steps + KS - 1) / KS;
-  G.my_delay = pos + G.wave * S::LAG;
-  G.lane0_delay = G.wave * (kWave + S::LAG);
-  G.lane63_delay = G.lane0_delay + kWave - 1;
+  G.my_delay = S::LL * pos + G.wave * S::LAG;
+  G.lane0_delay = G.wave * (S::LL * kWave + S::LAG);
+  G.lane63_delay = G.lane0_delay + S::LL * (kWave - 1);
   G.tiles_per_ckpt = CKPT ? p.ckpt_every / T : 1;
   G.ck_each_step = G.tiles_per_ckpt < KS;
 
@@ -347,15 +370,16 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     const int out_k = out_row - out_pos * R;
     const int out_wave = out_pos / kWave;
     G.out_lane = out_pos - out_wave * kWave;
-    G.out_delay = out_pos + out_wave * S::LAG;          // out lane's tile = step - out_delay
+    G.out_delay = S::LL * out_pos + out_wave * S::LAG;  // out lane's tile = step - out_delay
     const float* prev_row = pass > 0 ? row : nullptr;
 
-    // +inf handoff rings (a wave before its first tile must see +inf), then
-    // the first two intervals of reference and top boundary.
+    // +inf handoff rings and lane slots (a lane before its first tile must
+    // see +inf), then the first two intervals of reference and top boundary.
     for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = inf_f32();
+    for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = inf_f32();
     __syncthreads();
     {
-      Stager<R, T, W, KS> st0, st1;
+      Stager<R, T, W, KS, XL> st0, st1;
       st0.load(p.reference, p.ref_len, prev_row, G.ntiles * T, 0, tid);
       st1.load(p.reference, p.ref_len, prev_row, G.ntiles * T, KS, tid);
       st0.commit(s_ref, s_hand, 0, tid);
@@ -364,9 +388,9 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     __syncthreads();
 
     if (G.wave == out_wave) {
-      fwd_pass_out<0, R, T, W, KS, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand);
+      fwd_pass_out<0, R, T, W, KS, XL, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand, s_slot);
     } else {
-      fwd_pass<R, T, W, KS, KIND, CKPT, -1>(p, L, G, prev_row, s_ref, s_hand);
+      fwd_pass<R, T, W, KS, XL, KIND, CKPT, -1>(p, L, G, prev_row, s_ref, s_hand, s_slot);
     }
   }
 }
@@ -402,13 +426,14 @@ __device__ __forceinline__ void finish_query(const FwdParams& p, int b, const fl
 }
 
 // One workgroup per query.
-template <int R, int T, int W, int KS, int KIND, bool CKPT>
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) {
-  using S = FwdShape<R, T, W, KS>;
+  using S = FwdShape<R, T, W, KS, XL>;
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   const int b = blockIdx.x;
   float* row = p.rowbuf + (int64_t)b * p.row_stride;
-  fwd_query<R, T, W, KS, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T);
+  fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T,
+                                     s_mem + S::SR * T + W * S::SH * T);
   finish_query(p, b, row);
 }
 
@@ -416,9 +441,9 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) 
 // first) from a device counter; each workgroup owns one row-buffer slot and
 // reduces each finished query's last row in place.  Every workgroup leaves
 // the loop once the counter passes the batch size.
-template <int R, int T, int W, int KS, int KIND, bool CKPT>
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const FwdParams p) {
-  using S = FwdShape<R, T, W, KS>;
+  using S = FwdShape<R, T, W, KS, XL>;
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   __shared__ int s_item;
   float* row = p.rowbuf + (int64_t)blockIdx.x * p.row_stride;
@@ -437,7 +462,8 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const Fw
     __syncthreads();
     if (item >= p.batch) break;
     const int b = __builtin_amdgcn_readfirstlane(p.order[item]);
-    fwd_query<R, T, W, KS, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T);
+    fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T,
+                                     s_mem + S::SR * T + W * S::SH * T);
     finish_query(p, b, row);
   }
 }

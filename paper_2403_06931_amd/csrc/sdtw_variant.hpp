@@ -7,32 +7,33 @@
 namespace sdtw {
 
 struct Variant {
-  int R, T, W, KS;
+  int R, T, W, KS, XL;
   const void* plain[2][2];        // [cost kind][checkpoint]
   const void* persistent[2][2];
   int lds_bytes;
 };
 
-template <int R, int T, int W, int KS>
+template <int R, int T, int W, int KS, int XL>
 Variant make_variant() {
   Variant v;
   v.R = R;
   v.T = T;
   v.W = W;
   v.KS = KS;
-  v.plain[0][0] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, 0, false>);
-  v.plain[0][1] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, 0, true>);
-  v.plain[1][0] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, 1, false>);
-  v.plain[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, 1, true>);
-  v.persistent[0][0] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, 0, false>);
-  v.persistent[0][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, 0, true>);
-  v.persistent[1][0] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, 1, false>);
-  v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, 1, true>);
-  v.lds_bytes = (int)(sizeof(float) * FwdShape<R, T, W, KS>::LDS_FLOATS);
+  v.XL = XL;
+  v.plain[0][0] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, XL, 0, false>);
+  v.plain[0][1] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, XL, 0, true>);
+  v.plain[1][0] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, XL, 1, false>);
+  v.plain[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, XL, 1, true>);
+  v.persistent[0][0] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 0, false>);
+  v.persistent[0][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 0, true>);
+  v.persistent[1][0] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, false>);
+  v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, true>);
+  v.lds_bytes = (int)(sizeof(float) * FwdShape<R, T, W, KS, XL>::LDS_FLOATS);
   return v;
 }
 
 }  // namespace sdtw
 
 // Entry point of variant i, defined in the translation unit built for it.
-#define SDTW_DECLARE_VARIANT(i, R, T, W, KS) sdtw::Variant sdtw_variant_entry_##i();
+#define SDTW_DECLARE_VARIANT(i, R, T, W, KS, XL) sdtw::Variant sdtw_variant_entry_##i();

@@ -47,8 +47,9 @@ def test_variants_describe(L):
     n = P.sdtw_variant_count()
     assert n >= 1
     for v in range(n):
-        r, t, w, ks = P.sdtw_variant_info(v)
+        r, t, w, ks, xl = P.sdtw_variant_info(v)
         assert r >= 1 and t in (4, 8, 16) and 1 <= w <= 16 and ks in (8, 16, 32, 64)
+        assert xl in (0, 1)
         assert 16 % t == 0   # checkpoint intervals are multiples of 16
     with pytest.raises(P.SdtwError):
         P.sdtw_variant_info(n)
