@@ -1,5 +1,5 @@
-// sdtw_argmin.hpp -- reduction of the last DP row of a query to
-// (cost, end_pos).
+// sdtw_argmin.hpp -- lexicographic (value, index) reduction used to turn the
+// last DP row of a query into (cost, end_pos).
 //
 // cost = min_j D(N,j), end_pos = smallest 0-based j attaining it (the
 // walk-back of Section 2 starts from the minimum of the last row; Section 5.2
@@ -30,27 +30,6 @@ __device__ __forceinline__ ValIdx wave_argmin(ValIdx x) {
     o.i = __shfl_xor(x.i, d, kWave);
     x = better(x, o);
   }
-  return x;
-}
-
-// Block-wide lexicographic argmin of row[0..m); every thread gets the result.
-// Written without thread-dependent branches (all lanes of a wave hold the
-// same value after the butterfly and store it together), so it can sit in a
-// loop that also holds barriers.
-__device__ __forceinline__ ValIdx block_argmin(const float* __restrict__ row, int m) {
-  __shared__ ValIdx s_part[1024 / kWave];
-  ValIdx x{inf_f32(), 0x7fffffff};
-  for (int j = threadIdx.x; j < m; j += blockDim.x) {
-    const float v = row[j];
-    if (v < x.v) { x.v = v; x.i = j; }     // j increases: keeps the first minimiser
-  }
-  x = wave_argmin(x);
-  const int nw = (int)(blockDim.x / kWave);
-  s_part[threadIdx.x / kWave] = x;
-  __syncthreads();
-  x = s_part[0];
-  for (int k = 1; k < nw; ++k) x = better(x, s_part[k]);
-  __syncthreads();
   return x;
 }
 

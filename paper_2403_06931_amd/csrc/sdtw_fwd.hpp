@@ -23,14 +23,16 @@
 //     each wave lags the previous one by an extra LAG = KSTEP steps so that
 //     every handoff crosses a barrier;
 //   * reference tiles are staged from HBM into an LDS ring by the whole team,
-//     one interval ahead;
+//     two barrier intervals ahead;
 //   * queries longer than 64*R*W rows are processed in passes; the last row of
 //     a pass is written to a global row buffer that seeds the next pass.
 //
-// The last DP row (row N) is written to the same global row buffer; the
-// workgroup then reduces it to its minimum and first minimiser, giving cost
-// and end position (paper: Section 2, walk-back start
-// "the minimum valued tile in the last row"; Section 5.2 minimum reduction).
+// The lane holding the stored row writes its values for the step's tile to a
+// small LDS buffer.  After each barrier interval its wavefront copies them to
+// the row buffer (a pass's last row) or, for row N, folds them into a
+// per-lane running (minimum, first minimiser); at the end one wave reduction
+// gives cost and end position (Section 2 starts the walk-back from the minimum of the last row;
+// Section 5.2 reduces that row to its minimum).  Row N never goes to HBM.
 //
 // Lanes that are still before their first tile (tau < 0) hold +inf in every
 // register and only ever see +inf from their neighbours, so they stay +inf
@@ -83,7 +85,8 @@ struct FwdShape {
   static constexpr int ROWS = kWave * R * W;                  // rows per pass
   static constexpr int CHUNK = KS * T;                        // floats staged per interval
   static constexpr int SLOTS = XL ? W * kWave * T : 0;        // lane -> lane slots
-  static constexpr int LDS_FLOATS = SR * T + W * SH * T + SLOTS;
+  static constexpr int OUTBUF = KS * T;                       // row N over one interval
+  static constexpr int LDS_FLOATS = SR * T + W * SH * T + SLOTS + OUTBUF;
 };
 
 // Stage the reference tiles [tile0, tile0 + KS) and the wave-0 top boundary
@@ -149,6 +152,7 @@ struct LaneState {
   int ck_idx;      // index of the next checkpoint to store
   bool ck_pend;    // ckv holds a checkpoint column not yet stored
   float ckv[R];    // the lane's rows at the last checkpoint column reached
+  ValIdx am;       // running (minimum, first minimiser) of row N (its wavefront)
 };
 
 // Uniform (per wavefront) geometry of one pass.
@@ -158,8 +162,10 @@ struct PassGeom {
   int out_delay, out_lane;                   // lane holding the row to store
   int tiles_per_ckpt;
   bool ck_each_step;                         // store checkpoints every step
+  bool final_pass;                           // the stored row is row N
   int64_t qoff;
   float* row;                                // row-buffer slot of the query
+  float* s_out;                              // LDS: row N over one interval
 };
 
 // Store a captured checkpoint column.  Called once per barrier interval,
@@ -216,7 +222,10 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
     L.dl[k] = cur[T - 1];
     if (OUTK == k) {                            // folded once the k loop is unrolled
       if (do_out && G.lane == G.out_lane) {
-        float* dst = G.row + tau_out * T;
+        // to LDS only: at the interval's end the wave folds it (row N) or
+        // copies it to the row buffer (keeping a global store out of the
+        // step, whose LDS waits would otherwise cover it)
+        float* dst = G.s_out + (g & (KS - 1)) * T;
 #pragma unroll
         for (int t = 0; t < T; ++t) dst[t] = cur[t];
       }
@@ -276,6 +285,33 @@ __device__ __forceinline__ void step_inputs(float (&rv)[T], float (&top)[T], int
   }
 }
 
+// Fold the row-N values the out lane wrote during interval `it` (tiles
+// it*KS + s - out_delay, s < KS) into this lane's running (minimum, first
+// minimiser).  A lane sees the columns in increasing order, so a strict
+// comparison keeps the first minimiser.
+template <int T, int KS>
+__device__ __forceinline__ void out_fold(ValIdx& am, const PassGeom& G, int it, int ref_len) {
+  for (int e = G.lane; e < KS * T; e += kWave) {
+    const int tau = it * KS + e / T - G.out_delay;
+    const int j = tau * T + e % T;
+    const float v = G.s_out[e];
+    if (tau >= 0 && tau < G.ntiles && j < ref_len && v < am.v) {
+      am.v = v;
+      am.i = j;
+    }
+  }
+}
+
+// Copy the stored row's values of interval `it` from LDS to the row buffer
+// (a pass's last row, read by the next pass).
+template <int T, int KS>
+__device__ __forceinline__ void out_copy(const PassGeom& G, int it) {
+  for (int e = G.lane; e < KS * T; e += kWave) {
+    const int tau = it * KS + e / T - G.out_delay;
+    if (tau >= 0 && tau < G.ntiles) G.row[tau * T + e % T] = G.s_out[e];
+  }
+}
+
 // All barrier intervals of one pass.  The LDS inputs of step g+1 are read
 // while step g computes (two register sets, the step loop unrolled by two).
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK>
@@ -297,6 +333,13 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
       fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
     }
     if constexpr (CKPT) ckpt_flush(p, L, G);
+    if constexpr (OUTK >= 0) {
+      if (G.final_pass) {
+        out_fold<T, KS>(L.am, G, it, p.ref_len);
+      } else {
+        out_copy<T, KS>(G, it);
+      }
+    }
     st.commit(s_ref, s_hand, (it + 2) * KS, tid);
     __syncthreads();
   }
@@ -318,12 +361,16 @@ __device__ __forceinline__ void fwd_pass_out(int out_k, const FwdParams& p, Lane
   }
 }
 
-// Process every pass of query b with the team of W waves of this workgroup.
-// `row` is this query's row-buffer slot.
+// Process every pass of query b with the team of W waves of this workgroup
+// and store its cost and end position.  `row` is this query's row-buffer
+// slot (rows carried from one pass to the next).
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qoff,
-                                          float* __restrict__ row, float* s_ref, float* s_hand,
-                                          float* s_slot) {
+                                          float* __restrict__ row, float* s_mem) {
+  using S0 = FwdShape<R, T, W, KS, XL>;
+  float* s_ref = s_mem;
+  float* s_hand = s_ref + S0::SR * T;
+  float* s_slot = s_hand + W * S0::SH * T;
   using S = FwdShape<R, T, W, KS, XL>;
   const int tid = threadIdx.x;
   PassGeom G;
@@ -333,6 +380,7 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   G.n = __builtin_amdgcn_readfirstlane(p.lens[b]);     // uniform: loop bounds below
   G.qoff = qoff;
   G.row = row;
+  G.s_out = s_slot + S0::SLOTS;
   const float* __restrict__ q = p.queries + qoff;
   G.ntiles = (p.ref_len + T - 1) / T;
   const int npass = (G.n + S::ROWS - 1) / S::ROWS;
@@ -361,10 +409,12 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     L.ck_pend = false;
 #pragma unroll
     for (int k = 0; k < R; ++k) L.ckv[k] = 0.0f;
+    L.am = ValIdx{inf_f32(), 0x7fffffff};
 
-    // Row written to the row buffer by this pass: the pass's last row, or
-    // row N on the final pass.
+    // Row stored by this pass: the pass's last row (to the row buffer), or
+    // row N on the final pass (reduced on the fly).
     const bool last_pass = pass == npass - 1;
+    G.final_pass = last_pass;
     const int out_row = last_pass ? (G.n - 1 - prow0) : (S::ROWS - 1);
     const int out_pos = out_row / R;
     const int out_k = out_row - out_pos * R;
@@ -389,6 +439,13 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
 
     if (G.wave == out_wave) {
       fwd_pass_out<0, R, T, W, KS, XL, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand, s_slot);
+      if (last_pass) {
+        // every lane of the wave holds the result and stores it (no
+        // lane-dependent branch in a loop that holds barriers)
+        const ValIdx x = wave_argmin(L.am);
+        p.cost[b] = x.v;
+        p.end_pos[b] = x.i;
+      }
     } else {
       fwd_pass<R, T, W, KS, XL, KIND, CKPT, -1>(p, L, G, prev_row, s_ref, s_hand, s_slot);
     }
@@ -397,7 +454,7 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
 
 // Offset of query b in the packed batch: read from the offset table when the
 // host asked for one (large batches), else summed by the workgroup.  No
-// thread-dependent branch (see block_argmin).
+// thread-dependent branch (a loop of the persistent kernel holds barriers).
 __device__ __forceinline__ int64_t query_offset(const FwdParams& p, int b) {
   if (p.offsets != nullptr) return p.offsets[b];
   __shared__ unsigned long long s_off;
@@ -412,19 +469,6 @@ __device__ __forceinline__ int64_t query_offset(const FwdParams& p, int b) {
   return off;
 }
 
-// Reduce this query's last DP row (in its row-buffer slot) to cost and end
-// position.  The row was written by one lane of this workgroup; the barrier
-// makes it visible to every thread.  Wave 0 stores the result (all its
-// lanes store the same value).
-__device__ __forceinline__ void finish_query(const FwdParams& p, int b, const float* row) {
-  __syncthreads();
-  const ValIdx x = block_argmin(row, p.ref_len);
-  if (wave_id() == 0) {
-    p.cost[b] = x.v;
-    p.end_pos[b] = x.i;
-  }
-}
-
 // One workgroup per query.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) {
@@ -432,14 +476,12 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) 
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   const int b = blockIdx.x;
   float* row = p.rowbuf + (int64_t)b * p.row_stride;
-  fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T,
-                                     s_mem + S::SR * T + W * S::SH * T);
-  finish_query(p, b, row);
+  fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem);
 }
 
 // Persistent form: a fixed grid pops queries (in the given order, longest
-// first) from a device counter; each workgroup owns one row-buffer slot and
-// reduces each finished query's last row in place.  Every workgroup leaves
+// first) from a device counter; each workgroup owns one row-buffer slot
+// (for queries that need several passes).  Every workgroup leaves
 // the loop once the counter passes the batch size.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const FwdParams p) {
@@ -462,9 +504,7 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const Fw
     __syncthreads();
     if (item >= p.batch) break;
     const int b = __builtin_amdgcn_readfirstlane(p.order[item]);
-    fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem, s_mem + S::SR * T,
-                                     s_mem + S::SR * T + W * S::SH * T);
-    finish_query(p, b, row);
+    fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem);
   }
 }
 
