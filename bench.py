@@ -203,11 +203,10 @@ def fwd_bwd_leg(P, torch, steps, warmup):
     gq = torch.empty_like(q)
     gr = torch.empty_like(r)
 
-    # forward tile for this shape, timed without checkpoints (they add a few
-    # stores per K columns)
+    # forward tile for this shape, timed with checkpoints
     from paper_2403_06931_amd import autotune as A
     rec = {}
-    var = A.tune(q, w.lens, l, r, 0, 0, reps=2, record=rec)
+    var = A.tune(q, w.lens, l, r, 0, flags, reps=2, record=rec, ckpt=ckpt, ckpt_every=K)
 
     def fwd():
         P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, ckpt=ckpt, ckpt_every=K,

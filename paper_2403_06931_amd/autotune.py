@@ -67,8 +67,10 @@ def _store_cache(cache: Dict[str, dict]) -> None:
 
 
 def time_variant(variant: int, queries, h_lens, query_lens, reference, cost_kind: int,
-                 flags: int, reps: int = 5, warmup: int = 2, workspace_buf=None) -> float:
-    """Median milliseconds of one sdtw_forward call with this variant."""
+                 flags: int, reps: int = 5, warmup: int = 2, workspace_buf=None,
+                 ckpt=None, ckpt_every: int = 0) -> float:
+    """Median milliseconds of one sdtw_forward call with this variant (with
+    checkpoints when flags has SDTW_F_CHECKPOINT: pass ckpt and ckpt_every)."""
     h = api._host_lens(h_lens)
     dev = queries.device
     if workspace_buf is None:
@@ -76,7 +78,8 @@ def time_variant(variant: int, queries, h_lens, query_lens, reference, cost_kind
                                                                        flags), dev)
     cost = torch.empty(h.size, dtype=torch.float32, device=dev)
     end = torch.empty(h.size, dtype=torch.int64, device=dev)
-    kw = dict(cost=cost, end_pos=end, variant=variant, flags=flags, workspace_buf=workspace_buf)
+    kw = dict(cost=cost, end_pos=end, variant=variant, flags=flags, workspace_buf=workspace_buf,
+              ckpt=ckpt, ckpt_every=ckpt_every)
     for _ in range(warmup):
         api.sdtw_forward(queries, h, query_lens, reference, cost_kind, **kw)
     times: List[float] = []
@@ -93,7 +96,7 @@ def time_variant(variant: int, queries, h_lens, query_lens, reference, cost_kind
 
 def tune(queries, h_lens, query_lens, reference, cost_kind: int = 0, flags: int = 0,
          candidates: Optional[Sequence[int]] = None, reps: int = 5,
-         record: Optional[dict] = None) -> int:
+         record: Optional[dict] = None, ckpt=None, ckpt_every: int = 0) -> int:
     """Time every candidate variant on this batch; return the fastest."""
     h = api._host_lens(h_lens)
     if candidates is None:
@@ -103,7 +106,8 @@ def tune(queries, h_lens, query_lens, reference, cost_kind: int = 0, flags: int 
     results = {}
     for v in candidates:
         results[int(v)] = time_variant(int(v), queries, h, query_lens, reference, cost_kind,
-                                       flags, reps=reps, workspace_buf=ws)
+                                       flags, reps=reps, workspace_buf=ws, ckpt=ckpt,
+                                       ckpt_every=ckpt_every)
     best = min(results, key=results.get)
     if record is not None:
         record.update({"times_ms": results, "best": best})

@@ -148,9 +148,8 @@ struct LaneState {
   float dl[R];     // DP values of the lane's rows at the last column done
   float bot[T];    // the lane's bottom row over the last tile (feeds lane + 1)
   float corner;    // top boundary at the column before the current tile
-  int ck_cnt;      // steps until the next checkpoint column
-  int ck_idx;      // index of the next checkpoint to store
-  bool ck_pend;    // ckv holds a checkpoint column not yet stored
+  int ck_h;        // step at which the lane reaches its next checkpoint column
+  int ck_k;        // index of that checkpoint (0-based)
   float ckv[R];    // the lane's rows at the last checkpoint column reached
   ValIdx am;       // running (minimum, first minimiser) of row N (its wavefront)
 };
@@ -168,22 +167,28 @@ struct PassGeom {
   float* s_out;                              // LDS: row N over one interval
 };
 
-// Store a captured checkpoint column.  Called once per barrier interval,
-// or every step when checkpoints come closer than one interval apart, so a
-// lane never captures twice before storing.
+// Store the lane's rows at checkpoint column ck_k from `v` and move on to
+// the next checkpoint.
 template <int R, int T>
-__device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& L,
-                                           const PassGeom& G) {
-  if (L.ck_pend) {
-    if (L.ck_idx < p.n_ckpt) {
-      float* dst = p.ckpt + G.qoff * p.n_ckpt + (int64_t)L.ck_idx * G.n + G.row0;
+__device__ __forceinline__ void ckpt_store(const FwdParams& p, LaneState<R, T>& L,
+                                           const PassGeom& G, const float (&v)[R]) {
+  if (L.ck_k < p.n_ckpt) {
+    float* dst = p.ckpt + G.qoff * p.n_ckpt + (int64_t)L.ck_k * G.n + G.row0;
 #pragma unroll
-      for (int k = 0; k < R; ++k)
-        if (G.row0 + k < G.n) dst[k] = L.ckv[k];
-    }
-    ++L.ck_idx;
-    L.ck_pend = false;
+    for (int k = 0; k < R; ++k)
+      if (G.row0 + k < G.n) dst[k] = v[k];
   }
+  L.ck_h += G.tiles_per_ckpt;
+  ++L.ck_k;
+}
+
+// End of barrier interval `it`: store the checkpoint column captured in it,
+// if the lane reached one (checkpoints are at least one interval apart here,
+// so a lane reaches at most one per interval).
+template <int R, int T, int KS>
+__device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& L,
+                                           const PassGeom& G, int it) {
+  if (L.ck_h < (it + 1) * KS) ckpt_store(p, L, G, L.ckv);
 }
 
 // One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
@@ -252,17 +257,18 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
   }
 
   if constexpr (CKPT) {
-    // Checkpoint column kc*ckpt_every - 1 is the last column of a tile
-    // (ckpt_every is a multiple of T); a per-lane countdown finds it.  The
-    // lane's rows there are captured with selects and stored once per
-    // barrier interval (lanes reach the column on different steps).
-    --L.ck_cnt;
-    const bool hit = L.ck_cnt == 0;
-    L.ck_cnt = hit ? G.tiles_per_ckpt : L.ck_cnt;
+    // Checkpoint column kc*ckpt_every - 1 is the last column of tile
+    // kc*tpc - 1 (tpc = tiles per checkpoint; ckpt_every is a multiple of T),
+    // which the lane reaches at step my_delay + kc*tpc - 1.  The lane's rows
+    // there are captured with selects and stored at the interval's end, or
+    // right away when checkpoints come closer than one interval apart.
+    if (G.ck_each_step) {
+      if (g == L.ck_h) ckpt_store(p, L, G, L.dl);
+    } else {
+      const bool hit = g == L.ck_h;
 #pragma unroll
-    for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
-    L.ck_pend = L.ck_pend || hit;
-    if (G.ck_each_step) ckpt_flush(p, L, G);
+      for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
+    }
   }
 }
 
@@ -332,7 +338,14 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
       step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
       fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
     }
-    if constexpr (CKPT) ckpt_flush(p, L, G);
+    // The stager's commit waits for its loads with a vmcnt wait, which on
+    // gfx950 also covers every store issued before it; the interval's global
+    // stores (checkpoints, a pass's last row) therefore come after the
+    // commit and complete while the next interval computes.
+    st.commit(s_ref, s_hand, (it + 2) * KS, tid);
+    if constexpr (CKPT) {
+      if (!G.ck_each_step) ckpt_flush<R, T, KS>(p, L, G, it);
+    }
     if constexpr (OUTK >= 0) {
       if (G.final_pass) {
         out_fold<T, KS>(L.am, G, it, p.ref_len);
@@ -340,7 +353,6 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
         out_copy<T, KS>(G, it);
       }
     }
-    st.commit(s_ref, s_hand, (it + 2) * KS, tid);
     __syncthreads();
   }
 }
@@ -404,9 +416,8 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
 #pragma unroll
     for (int t = 0; t < T; ++t) L.bot[t] = inf_f32();
     L.corner = inf_f32();
-    L.ck_cnt = G.tiles_per_ckpt + G.my_delay;          // steps until tau = tiles_per_ckpt-1
-    L.ck_idx = 0;
-    L.ck_pend = false;
+    L.ck_h = G.my_delay + G.tiles_per_ckpt - 1;        // reaches checkpoint 0 there
+    L.ck_k = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) L.ckv[k] = 0.0f;
     L.am = ValIdx{inf_f32(), 0x7fffffff};
