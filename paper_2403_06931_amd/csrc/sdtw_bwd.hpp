@@ -47,15 +47,19 @@ constexpr int kDirMaxRows = 8192;               // query + left column held in L
 constexpr int kWalkChunk = 64;                  // code rows per walker LDS chunk
 constexpr int kBwdMaxSlots = 8;                 // blocks per round per query
 
-// Direction code of a cell, 2 bits (cell c of a word at bits 2c, 2c+1):
-// bit 0 = "the diagonal is not a minimum", bit 1 = "the cell above is not a
-// minimum".  The walk steps diagonally if bit 0 is clear, else up if bit 1 is
-// clear, else left (ties: diagonal, then up, then left).  DP values are
-// never negative (nor -0), so their bit patterns order like the values and
-// x != min is the unsigned difference of the patterns clamped to 1.
-__device__ __forceinline__ uint32_t not_min_bit(float x, float mn) {
-  const uint32_t d = __builtin_bit_cast(uint32_t, x) - __builtin_bit_cast(uint32_t, mn);
-  return d < 1u ? d : 1u;
+// Direction code of a cell, 2 bits: a = "the diagonal is not a minimum",
+// u = "the cell above is not a minimum".  The walk steps diagonally if a is
+// clear, else up if u is clear, else left (ties: diagonal, then up, then
+// left).  A lane's 16 cells of a row fill one word from the top: cell c's a
+// is bit 2(15-c)+1 and its u is bit 2(15-c).
+//
+// Shift "x is not a minimum" into the word from below.  DP values are never
+// negative (nor -0), so their bit patterns order like the values: for
+// x >= mn, bits(mn) - bits(x) is zero or has its sign bit set, and
+// v_alignbit_b32 forms (word << 1) | (that sign bit) in one instruction.
+__device__ __forceinline__ uint32_t push_not_min(uint32_t word, float x, float mn) {
+  const uint32_t d = __builtin_bit_cast(uint32_t, mn) - __builtin_bit_cast(uint32_t, x);
+  return __builtin_amdgcn_alignbit(word, d, 31);
 }
 
 struct BwdParams {
@@ -149,8 +153,8 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, const floa
   for (int c = 0; c < kDirCols; ++c) {
     const float up = dprev[c];
     const float mn = min3(up, left, diag);
-    word |= not_min_bit(diag, mn) << (2 * c);
-    word |= not_min_bit(up, mn) << (2 * c + 1);
+    word = push_not_min(word, diag, mn);
+    word = push_not_min(word, up, mn);
     cur[c] = mn + local_cost<KIND>(qv, rv[c]);
     diag = up;
     left = cur[c];
@@ -313,16 +317,17 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
         const uint32_t w =
             (uint32_t)wave_uniform((int)chunk[(g - k * kWalkChunk) * kWave + L]);
         // pass through the cells c, c-1, ... of this word whose code is
-        // "left"; the first other one ends the run in this row
-        const uint32_t is_left = (w >> 1) & w & 0x55555555u;
-        const uint32_t upto = c == kDirCols - 1 ? 0xffffffffu : ((1u << (2 * c + 2)) - 1u);
-        const uint32_t stop = ~is_left & 0x55555555u & upto;
+        // "left" (cell c' is bit pair 15-c'); the first other one ends the
+        // run in this row
+        const uint32_t is_left = (w >> 1) & w & 0x55555555u;   // at bit 2(15-c')
+        const int pc = kDirCols - 1 - c;
+        const uint32_t stop = ~is_left & 0x55555555u & (~0u << (2 * pc));
         if (stop == 0) {
           j -= c + 1;                           // into the previous lane's columns
           continue;
         }
-        const int bit = 31 - __builtin_clz(stop);
-        j -= c - (bit >> 1);
+        const int bit = __builtin_ctz(stop);    // 2(15-c') for the cell c' that stops
+        j -= (bit >> 1) - pc;
         if (i == 1) {                           // the start cell
           if (lane == 0) {
             rlo[1] = j;
@@ -331,7 +336,7 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
           done = 1;
           break;
         }
-        const bool diagonal = ((w >> bit) & 1u) == 0;
+        const bool diagonal = ((w >> (bit + 1)) & 1u) == 0;
         if (lane == 0) rlo[i] = j;
         i -= 1;
         if (diagonal) j -= 1;
