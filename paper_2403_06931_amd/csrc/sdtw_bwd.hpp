@@ -138,14 +138,22 @@ __global__ __launch_bounds__(kInitThreads) void sdtw_bwd_init_kernel(const BwdPa
 
 // One row step of the direction recompute.  MASKED: some lanes are outside
 // rows 1..nrows and keep their state (row 0 before they start).
+// Lane 0's inputs of step g (row g+1): the segment's left column and the
+// query value, read one step ahead of their use.
+__device__ __forceinline__ void dirs_inputs(int g, int nrows, const float* lq, const float* ledge,
+                                            float& il, float& iq) {
+  const int gi = g < nrows ? g : nrows - 1;
+  il = ledge[gi];
+  iq = lq[gi];
+}
+
 template <int KIND, bool MASKED>
-__device__ __forceinline__ void dirs_step(int g, int lane, int nrows, const float* lq,
+__device__ __forceinline__ void dirs_step(int g, int lane, int nrows, float il, float iq,
                                           float* ledge, const float (&rv)[kDirCols],
                                           float (&dprev)[kDirCols], float& last, float& shp,
                                           float& qv, uint32_t* __restrict__ out) {
-  const int gi = g < nrows ? g : nrows - 1;
-  const float shc = wave_shr1(ledge[gi], last);   // left neighbour on this row
-  qv = wave_shr1(lq[gi], qv);                     // this row's query value
+  const float shc = wave_shr1(il, last);          // left neighbour on this row
+  qv = wave_shr1(iq, qv);                         // this row's query value
   float cur[kDirCols];
   uint32_t word = 0;
   float left = shc, diag = shp;
@@ -234,17 +242,29 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
     float last = 0.0f, shp = 0.0f, qv = 0.0f;
     const int g_end = nrows + kWave - 1;
     const int g_head = g_end < kWave - 1 ? g_end : kWave - 1;
+    // (lane 63 writes ledge[g-63] at step g, long after it was read)
+    float ilA, iqA, ilB, iqB;
+    dirs_inputs(0, nrows, lq, ledge, ilA, iqA);
     int g = 0;
-    for (; g < g_head; ++g)
-      dirs_step<KIND, true>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
-    for (; g + 1 < nrows; g += 2) {
-      dirs_step<KIND, false>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
-      dirs_step<KIND, false>(g + 1, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+    for (; g < g_head; ++g) {
+      dirs_inputs(g + 1, nrows, lq, ledge, ilB, iqB);
+      dirs_step<KIND, true>(g, lane, nrows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out);
+      ilA = ilB;
+      iqA = iqB;
     }
-    for (; g < nrows; ++g)
-      dirs_step<KIND, false>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
-    for (; g < g_end; ++g)
-      dirs_step<KIND, true>(g, lane, nrows, lq, ledge, rv, dprev, last, shp, qv, out);
+    for (; g + 1 < nrows; g += 2) {
+      dirs_inputs(g + 1, nrows, lq, ledge, ilB, iqB);
+      dirs_step<KIND, false>(g, lane, nrows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out);
+      dirs_inputs(g + 2, nrows, lq, ledge, ilA, iqA);
+      dirs_step<KIND, false>(g + 1, lane, nrows, ilB, iqB, ledge, rv, dprev, last, shp, qv,
+                             out);
+    }
+    for (; g < g_end; ++g) {
+      dirs_inputs(g + 1, nrows, lq, ledge, ilB, iqB);
+      dirs_step<KIND, true>(g, lane, nrows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out);
+      ilA = ilB;
+      iqA = iqB;
+    }
   }
 }
 
