@@ -18,7 +18,10 @@ Prints ONE JSON line.  Beside the headline value it reports:
                 250..4,000 samples vs 200,000) and the same batch run as a
                 loop of plain launches over 16 length buckets;
   fwd_bwd       forward with checkpoints plus the walk-back gradient
-                (256 x 1,000 vs 50,000).
+                (256 x 1,000 vs 50,000);
+  znorm         the batch z-normaliser that prepares the inputs, against
+                the 8 TB/s HBM roofline (8 algorithmic bytes per sample:
+                one read, one write).
 """
 import argparse
 import hashlib
@@ -234,6 +237,39 @@ def fwd_bwd_leg(P, torch, steps, warmup):
             "variant": P.sdtw_variant_info(var), "tuned_over": len(rec.get("times_ms", {}))}
 
 
+HBM_PEAK_GBS = 8000.0
+
+
+def znorm_leg(P, torch, steps, warmup):
+    """sdtw_znorm on raw (unnormalised) series of the evaluation's shapes."""
+    import numpy as np
+
+    import workloads
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(240306931)
+    sets = {
+        "512x2000+100k": [2000] * 512 + [100_000],
+        "4096xU[250,4000]": list(rng.integers(250, 4001, 4096)),
+        "2M": [2_000_000],
+    }
+    out = {}
+    for name, lens in sets.items():
+        x = torch.from_numpy(workloads.raw_series(lens, seed=len(lens))).to(dev)
+        h = np.asarray(lens, np.int32)
+        lt = torch.from_numpy(h).to(dev)
+        z = torch.empty_like(x)
+        wsb = P.workspace(P.sdtw_znorm_workspace_bytes(h), dev)
+
+        def run():
+            P.sdtw_znorm(x, h, lt, out=z, workspace_buf=wsb)
+        wall_ms, ev_ms = time_steps(run, steps, warmup, torch)
+        gbs = 8.0 * x.numel() / (ev_ms * 1e6)
+        out[name] = {"samples": int(x.numel()), "ms": ev_ms, "wall_ms": wall_ms,
+                     "GB/s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    return {"bound": "hbm", "peak_GB/s": HBM_PEAK_GBS,
+            "bytes_per_sample": 8, "sets": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +280,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
     ap.add_argument("--valu-issue-probe", action="store_true",
                     help="only measure the FP32 VALU issue rate (bench_valu_issue.hip) and exit")
+    ap.add_argument("--znorm-only", action="store_true",
+                    help="only time the batch z-normaliser (sdtw_znorm) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's built-in variant choice instead of timing all variants")
     args = ap.parse_args()
@@ -264,6 +302,11 @@ def main():
 
     import paper_2403_06931_amd as P
     import workloads
+
+    if args.znorm_only:
+        print(json.dumps({"znorm": znorm_leg(P, torch, steps=args.steps, warmup=args.warmup)}),
+              flush=True)
+        return
 
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(dev)
@@ -329,6 +372,7 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(P, torch, steps=3, warmup=1)
         out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1)
+        out["znorm"] = znorm_leg(P, torch, steps=20, warmup=3)
     print(json.dumps(out), flush=True)
 
 

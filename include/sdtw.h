@@ -183,6 +183,36 @@ SDTW_API int sdtw_backward(const float *queries, const int32_t *h_query_lens,
                   float *grad_queries, float *grad_reference,
                   void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * Batch z-normalisation, the step that prepares queries and reference
+ * (paper: Section 3, "Normalizer implementation", standardisation equation):
+ * every series of a packed batch becomes
+ *
+ *     z_k = (x_k - mean) / S,   mean = (1/n) sum x_k,
+ *     S = sqrt((1/n) sum (x_k - mean)^2)   (population standard deviation),
+ *
+ * with mean, S and the quotient in binary64 and z rounded once to binary32.
+ * A constant series (S = 0) maps to zeros (the paper leaves it open).
+ * Chunk sums are reduced in a fixed order, so the result does not depend on
+ * scheduling; it may differ from another binary64 evaluation order by one
+ * binary32 ulp.
+ *
+ *   x             packed float32 series [sum h_lens] (packed like queries)
+ *   h_lens/lens   host / device int32 [batch] series lengths, each >= 1
+ *   z             float32 output packed like x; either equal to x (in place)
+ *                 or not overlapping it
+ *   workspace     sdtw_znorm_workspace_bytes(h_lens, batch) bytes, 256-byte
+ *                 aligned; contents on return are unspecified
+ *
+ * Returns SDTW_OK, SDTW_ERR_INVALID_ARG (null pointer, batch < 1, a length
+ * < 1, misaligned workspace), SDTW_ERR_WORKSPACE or SDTW_ERR_HIP.
+ */
+SDTW_API size_t sdtw_znorm_workspace_bytes(const int32_t *h_lens, int32_t batch);
+
+SDTW_API int sdtw_znorm(const float *x, const int32_t *h_lens, const int32_t *lens,
+                        int32_t batch, float *z, void *workspace, size_t workspace_bytes,
+                        void *stream);
+
 /* Number of compiled forward tile variants. */
 SDTW_API int32_t sdtw_variant_count(void);
 

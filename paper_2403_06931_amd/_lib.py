@@ -62,6 +62,10 @@ def _load():
                                   ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
                                   _vp, ctypes.c_size_t, _vp]
     lib.sdtw_backward.restype = ctypes.c_int
+    lib.sdtw_znorm_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
+    lib.sdtw_znorm_workspace_bytes.restype = ctypes.c_size_t
+    lib.sdtw_znorm.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.sdtw_znorm.restype = ctypes.c_int
     return lib
 
 

@@ -160,3 +160,34 @@ def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
         _stream(stream))
     check(st, "sdtw_backward")
     return grad_queries, grad_reference
+
+
+def sdtw_znorm_workspace_bytes(h_lens) -> int:
+    h = _host_lens(h_lens)
+    return int(_lib.lib.sdtw_znorm_workspace_bytes(_hp(h), h.size))
+
+
+def sdtw_znorm(x: torch.Tensor, h_lens, lens: torch.Tensor, *,
+               out: Optional[torch.Tensor] = None,
+               workspace_buf: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+    """Z-normalise every series of the packed batch x (float32, lengths h_lens);
+    out may be x itself."""
+    h = _host_lens(h_lens)
+    _require_cuda("x", x, torch.float32)
+    _require_cuda("lens", lens, torch.int32)
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _require_cuda("out", out, torch.float32)
+    if out.numel() != x.numel():
+        raise ValueError("out must have the size of x")
+    need = sdtw_znorm_workspace_bytes(h)
+    if need == 0:
+        raise SdtwError(_lib.SDTW_ERR_INVALID_ARG, "sdtw_znorm_workspace_bytes")
+    if workspace_buf is None:
+        workspace_buf = workspace(need, x.device)
+    st = _lib.lib.sdtw_znorm(_dp(x), _hp(h), _dp(lens), h.size, _dp(out), _dp(workspace_buf),
+                             workspace_buf.numel(), _stream(stream))
+    check(st, "sdtw_znorm")
+    return out

@@ -13,6 +13,7 @@
 #include "sdtw_fwd.hpp"
 #include "sdtw_setup.hpp"
 #include "sdtw_variant.hpp"
+#include "sdtw_znorm.hpp"
 
 #include "sdtw_variants.inc"
 SDTW_VARIANTS(SDTW_DECLARE_VARIANT)
@@ -203,6 +204,34 @@ BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t 
   L.codes = at;
   L.code_half = (int64_t)(words_per_slot * (size_t)slots);
   at = align_up(at + 2 * bytes_per_slot * (size_t)slots, kAlign);
+  L.total = at;
+  return L;
+}
+
+// Normaliser workspace: element and chunk offsets, chunk -> series map and
+// the binary64 chunk partials.
+struct ZLayout {
+  size_t offsets, chunk_off, chunk_series, part, total;
+  int64_t chunks;
+  bool multi;                   // some series spans several chunks
+};
+
+ZLayout znorm_layout(const int32_t* h_lens, int32_t batch) {
+  ZLayout L{};
+  for (int32_t b = 0; b < batch; ++b) {
+    const int64_t c = sdtw::znorm_chunks_of(h_lens[b]);
+    L.chunks += c;
+    L.multi = L.multi || c > 1;
+  }
+  size_t at = 0;
+  L.offsets = at;
+  at = align_up(at + sizeof(int64_t) * ((size_t)batch + 1), kAlign);
+  L.chunk_off = at;
+  at = align_up(at + sizeof(int64_t) * ((size_t)batch + 1), kAlign);
+  L.chunk_series = at;
+  at = align_up(at + sizeof(int32_t) * (size_t)L.chunks, kAlign);
+  L.part = at;
+  at = align_up(at + 2 * sizeof(double) * (size_t)L.chunks, kAlign);
   L.total = at;
   return L;
 }
@@ -465,6 +494,48 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
     return launch(reinterpret_cast<const void*>(&sdtw::sdtw_ref_reduce_kernel), dim3(grid),
                   dim3(sdtw::kRefReduceThreads), args, stream);
   }
+}
+
+size_t sdtw_znorm_workspace_bytes(const int32_t* h_lens, int32_t batch) {
+  if (!lens_ok(h_lens, batch, nullptr, nullptr)) return 0;
+  return znorm_layout(h_lens, batch).total;
+}
+
+int sdtw_znorm(const float* x, const int32_t* h_lens, const int32_t* lens, int32_t batch,
+               float* z, void* workspace, size_t workspace_bytes, void* stream_ptr) {
+  if (!x || !lens || !z || !workspace) return SDTW_ERR_INVALID_ARG;
+  if (!lens_ok(h_lens, batch, nullptr, nullptr)) return SDTW_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  const ZLayout L = znorm_layout(h_lens, batch);
+  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+  if (L.chunks > INT32_MAX) return SDTW_ERR_UNSUPPORTED;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+  char* ws = static_cast<char*>(workspace);
+  sdtw::ZParams p{};
+  p.x = x;
+  p.z = z;
+  p.lens = lens;
+  p.offsets = reinterpret_cast<int64_t*>(ws + L.offsets);
+  p.chunk_off = reinterpret_cast<int64_t*>(ws + L.chunk_off);
+  p.chunk_series = reinterpret_cast<int32_t*>(ws + L.chunk_series);
+  p.part = reinterpret_cast<double*>(ws + L.part);
+  p.batch = batch;
+  {
+    int64_t* off = reinterpret_cast<int64_t*>(ws + L.offsets);
+    int64_t* coff = reinterpret_cast<int64_t*>(ws + L.chunk_off);
+    int32_t* cser = reinterpret_cast<int32_t*>(ws + L.chunk_series);
+    void* args[] = {(void*)&lens, (void*)&batch, (void*)&off, (void*)&coff, (void*)&cser};
+    const int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_index_kernel), dim3(1),
+                          dim3(sdtw::kScanThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  void* args[] = {(void*)&p};
+  const dim3 grid((unsigned)L.chunks);
+  int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_stats_kernel), grid,
+                  dim3(sdtw::kZThreads), args, stream);
+  if (rc != SDTW_OK || !L.multi) return rc;
+  return launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_apply_kernel), grid,
+                dim3(sdtw::kZThreads), args, stream);
 }
 
 }  // extern "C"

@@ -1,0 +1,184 @@
+// sdtw_znorm.hpp -- batch z-normalisation, the step before the DP (the
+// paper's normaliser, Section 3 "Normalizer implementation", standardisation
+// equation): every series of a packed batch becomes z = (x - mean) / S with S
+// the population standard deviation.  Included by the API translation unit
+// only.
+//
+// Layout.  A series is cut into chunks of kZChunk elements; one 256-thread
+// workgroup owns a chunk and keeps it in registers (16 values per thread,
+// loads coalesced across the workgroup).  The per-chunk sum and the sum of
+// squared deviations from the chunk mean are reduced in binary64.  A series
+// of one chunk (every query of the paper's workloads) is finished by the same
+// workgroup: one HBM read and one write per element, which is the bound.  A
+// longer series (a reference) stores its chunk partials; a second kernel
+// combines them exactly in fixed order (sum of squares = sum over chunks of
+// the chunk's own sum plus n_k (mean_k - mean)^2) and writes z after reading
+// the chunk once more.  All reductions run in a fixed order, so results do
+// not depend on scheduling; z is rounded once, from binary64, to binary32.
+#pragma once
+
+#include "sdtw_common.hpp"
+#include "sdtw_setup.hpp"
+
+namespace sdtw {
+
+constexpr int kZThreads = 256;                  // 4 wavefronts
+constexpr int kZPer = 16;                       // elements per thread
+constexpr int kZChunk = kZThreads * kZPer;      // elements per workgroup
+
+struct ZParams {
+  const float* x;               // packed input series
+  float* z;                     // packed output (may equal x)
+  const int32_t* lens;          // [batch]
+  const int64_t* offsets;       // [batch + 1] first element of each series
+  const int64_t* chunk_off;     // [batch + 1] first chunk of each series
+  const int32_t* chunk_series;  // [chunks] series of each chunk
+  double* part;                 // [chunks][2] chunk sum, chunk sum of squared deviations
+  int32_t batch;
+};
+
+__host__ __device__ constexpr int64_t znorm_chunks_of(int64_t n) {
+  return (n + kZChunk - 1) / kZChunk;
+}
+
+// Element and chunk offsets of every series and the series of every chunk,
+// in one workgroup (the scan of sdtw_offsets_kernel, over two quantities).
+__global__ __launch_bounds__(kScanThreads) void sdtw_znorm_index_kernel(
+    const int32_t* __restrict__ lens, int32_t batch, int64_t* __restrict__ offsets,
+    int64_t* __restrict__ chunk_off, int32_t* __restrict__ chunk_series) {
+  __shared__ int64_t s_el[kScanThreads];
+  __shared__ int64_t s_ch[kScanThreads];
+  const int tid = threadIdx.x;
+  const int per = (batch + kScanThreads - 1) / kScanThreads;
+  const int lo = min(batch, tid * per), hi = min(batch, lo + per);
+  int64_t el = 0, ch = 0;
+  for (int i = lo; i < hi; ++i) {
+    el += lens[i];
+    ch += znorm_chunks_of(lens[i]);
+  }
+  s_el[tid] = el;
+  s_ch[tid] = ch;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const int64_t a = tid >= d ? s_el[tid - d] : 0;
+    const int64_t c = tid >= d ? s_ch[tid - d] : 0;
+    __syncthreads();
+    s_el[tid] += a;
+    s_ch[tid] += c;
+    __syncthreads();
+  }
+  int64_t re = s_el[tid] - el, rc = s_ch[tid] - ch;
+  for (int i = lo; i < hi; ++i) {
+    offsets[i] = re;
+    chunk_off[i] = rc;
+    const int64_t nc = znorm_chunks_of(lens[i]);
+    for (int64_t k = 0; k < nc; ++k) chunk_series[rc + k] = i;
+    re += lens[i];
+    rc += nc;
+  }
+  if (tid == kScanThreads - 1) {
+    offsets[batch] = s_el[tid];
+    chunk_off[batch] = s_ch[tid];
+  }
+}
+
+// Sum over the workgroup in a fixed order: a butterfly within each
+// wavefront (every lane ends with the same bits, since each step adds the
+// same two values), then the wavefront sums in index order.
+__device__ __forceinline__ double znorm_block_sum(double v, double* red) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int w = 1; w < kZThreads / kWave; ++w) s += red[w];
+  __syncthreads();                              // red is reused by the next call
+  return s;
+}
+
+struct ZChunk {
+  int b, n, k, nch, m;          // series, its length, chunk index, chunks, elements here
+  int64_t c0, start;            // series' first chunk, first element of this chunk
+};
+
+__device__ __forceinline__ ZChunk znorm_chunk(const ZParams& p, int c) {
+  ZChunk q;
+  q.b = p.chunk_series[c];
+  q.n = p.lens[q.b];
+  q.c0 = p.chunk_off[q.b];
+  q.nch = (int)(p.chunk_off[q.b + 1] - q.c0);
+  q.k = (int)(c - q.c0);
+  q.start = p.offsets[q.b] + (int64_t)q.k * kZChunk;
+  q.m = min(kZChunk, q.n - q.k * kZChunk);
+  return q;
+}
+
+__device__ __forceinline__ void znorm_load(const ZParams& p, const ZChunk& q, float (&v)[kZPer]) {
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    const int i = threadIdx.x + u * kZThreads;
+    v[u] = i < q.m ? p.x[q.start + i] : 0.0f;
+  }
+}
+
+__device__ __forceinline__ void znorm_store(const ZParams& p, const ZChunk& q,
+                                            const float (&v)[kZPer], double mean, double s) {
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    const int i = threadIdx.x + u * kZThreads;
+    if (i < q.m) p.z[q.start + i] = s > 0.0 ? (float)(((double)v[u] - mean) / s) : 0.0f;
+  }
+}
+
+// Chunk statistics; series of one chunk are standardised here.
+// Grid: one workgroup per chunk.
+__global__ __launch_bounds__(kZThreads) void sdtw_znorm_stats_kernel(const ZParams p) {
+  __shared__ double red[kZThreads / kWave];
+  const ZChunk q = znorm_chunk(p, blockIdx.x);
+  float v[kZPer];
+  znorm_load(p, q, v);
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) s += (double)v[u];     // padding adds +0
+  const double s1 = znorm_block_sum(s, red);
+  const double mk = s1 / q.m;
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    if (threadIdx.x + u * kZThreads < q.m) {
+      const double d = (double)v[u] - mk;
+      t += d * d;
+    }
+  }
+  const double m2 = znorm_block_sum(t, red);
+  if (q.nch == 1) {
+    znorm_store(p, q, v, mk, __builtin_sqrt(m2 / q.n));
+  } else if (threadIdx.x == 0) {
+    p.part[2 * (int64_t)blockIdx.x] = s1;
+    p.part[2 * (int64_t)blockIdx.x + 1] = m2;
+  }
+}
+
+// Series of several chunks: combine the chunk partials, then standardise
+// this workgroup's chunk.  Grid: one workgroup per chunk.
+__global__ __launch_bounds__(kZThreads) void sdtw_znorm_apply_kernel(const ZParams p) {
+  __shared__ double red[kZThreads / kWave];
+  const ZChunk q = znorm_chunk(p, blockIdx.x);
+  if (q.nch == 1) return;
+  double s = 0.0;
+  for (int k = threadIdx.x; k < q.nch; k += kZThreads) s += p.part[2 * (q.c0 + k)];
+  const double mean = znorm_block_sum(s, red) / q.n;
+  double t = 0.0;
+  for (int k = threadIdx.x; k < q.nch; k += kZThreads) {
+    const int mk_n = min(kZChunk, q.n - k * kZChunk);
+    const double d = p.part[2 * (q.c0 + k)] / mk_n - mean;
+    t += p.part[2 * (q.c0 + k) + 1] + mk_n * (d * d);
+  }
+  const double sd = __builtin_sqrt(znorm_block_sum(t, red) / q.n);
+  float v[kZPer];
+  znorm_load(p, q, v);
+  znorm_store(p, q, v, mean, sd);
+}
+
+}  // namespace sdtw

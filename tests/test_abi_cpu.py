@@ -150,3 +150,31 @@ def test_backward_workspace_sizes(L):
     assert P.sdtw_backward_workspace_bytes(np.array([8193], np.int32), 100, 64) == 0
     assert P.sdtw_backward_workspace_bytes(lens, 50000, 0) == 0
     assert P.sdtw_backward_workspace_bytes(lens, 50000, 24) == 0
+
+
+def _zn(L, lens, batch=None, x=FAKE, dlens=FAKE, z=FAKE, ws=FAKE, ws_bytes=1 << 40):
+    h = np.ascontiguousarray(lens, dtype=np.int32)
+    b = h.size if batch is None else batch
+    return L.lib.sdtw_znorm(_vp(x), _vp(h.ctypes.data if h.size else 0), _vp(dlens), b, _vp(z),
+                            _vp(ws), ws_bytes, _vp(0))
+
+
+def test_znorm_rejects_invalid_arguments(L):
+    E = L.SDTW_ERR_INVALID_ARG
+    for name in ("x", "dlens", "z", "ws"):
+        assert _zn(L, [3, 4], **{name: 0}) == E, name
+    assert _zn(L, [3, 0]) == E
+    assert _zn(L, [3, -1]) == E
+    assert _zn(L, [3, 4], batch=0) == E
+    assert _zn(L, [3, 4], ws=FAKE + 8) == E
+    assert _zn(L, [3, 4], ws_bytes=16) == L.SDTW_ERR_WORKSPACE
+
+
+def test_znorm_workspace_sizes(L):
+    import paper_2403_06931_amd as P
+    a = P.sdtw_znorm_workspace_bytes(np.array([10, 20], np.int32))
+    b = P.sdtw_znorm_workspace_bytes(np.array([10, 2_000_000], np.int32))
+    assert 0 < a < b
+    # 16 bytes of binary64 partials per 4,096-element chunk at least
+    assert b >= 16 * (2_000_000 // 4096)
+    assert P.sdtw_znorm_workspace_bytes(np.array([10, 0], np.int32)) == 0

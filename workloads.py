@@ -204,3 +204,19 @@ def digest(w: Workload) -> str:
     for a in (w.queries, w.lens, w.reference):
         h.update(np.ascontiguousarray(a).tobytes())
     return h.hexdigest()
+
+
+def raw_series(lens, seed: int) -> np.ndarray:
+    """Packed float32 series before any normalisation, as captured in
+    different units: per series a Gaussian random walk (or, for every fourth
+    series, white noise) times a scale drawn log-uniformly from [1e-3, 1e3],
+    plus an offset of up to 50 scales."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, n in enumerate(lens):
+        n = int(n)
+        base = rng.standard_normal(n) if k % 4 == 3 else np.cumsum(rng.standard_normal(n))
+        scale = 10.0 ** rng.uniform(-3.0, 3.0)
+        offset = rng.uniform(-50.0, 50.0) * scale
+        out.append((base * scale + offset).astype(np.float32))
+    return np.concatenate(out) if out else np.zeros(0, np.float32)
