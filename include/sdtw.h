@@ -184,6 +184,40 @@ SDTW_API int sdtw_backward(const float *queries, const int32_t *h_query_lens,
                   void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Alignment path of every query (paper: Section 2, the walk back from the
+ * minimum of the last row that recovers the optimal warping path), from the
+ * outputs of an sdtw_forward call made with SDTW_F_CHECKPOINT.  The walk
+ * starts at (N, end_pos), steps to the smallest of the diagonal, upper and
+ * left neighbours (ties: diagonal, then up, then left) and stops on row 1.
+ * Query element i (row i+1, packed index off_b + i) is matched to reference
+ * elements path_lo[off_b + i] .. path_hi[off_b + i] (0-based, inclusive);
+ * row ranges are contiguous and consecutive rows touch (path_hi of row i is
+ * path_lo of row i+1 or one less).  start_pos[b] = path_lo of query b's
+ * first element, so the matched subsequence is reference[start_pos ..
+ * end_pos].
+ *
+ *   cost, end_pos         the forward's outputs for the same inputs
+ *   ckpt, ckpt_every      the forward's checkpoint columns and interval
+ *   start_pos             int64 [batch]
+ *   path_lo, path_hi      int32, packed like queries
+ *   workspace             sdtw_align_workspace_bytes(...) bytes, 256-byte
+ *                         aligned
+ *
+ * Same limits and status codes as sdtw_backward (queries of at most 8,192
+ * rows, ckpt_every a positive multiple of 16).
+ */
+SDTW_API size_t sdtw_align_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
+                                           int64_t ref_len, int32_t ckpt_every);
+
+SDTW_API int sdtw_align(const float *queries, const int32_t *h_query_lens,
+                        const int32_t *query_lens, int32_t batch,
+                        const float *reference, int64_t ref_len, int32_t cost_kind,
+                        const float *cost, const int64_t *end_pos,
+                        const float *ckpt, int32_t ckpt_every,
+                        int64_t *start_pos, int32_t *path_lo, int32_t *path_hi,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Batch z-normalisation, the step that prepares queries and reference
  * (paper: Section 3, "Normalizer implementation", standardisation equation):
  * every series of a packed batch becomes

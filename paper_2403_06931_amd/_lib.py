@@ -62,6 +62,13 @@ def _load():
                                   ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
                                   _vp, ctypes.c_size_t, _vp]
     lib.sdtw_backward.restype = ctypes.c_int
+    lib.sdtw_align_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64,
+                                               ctypes.c_int32]
+    lib.sdtw_align_workspace_bytes.restype = ctypes.c_size_t
+    lib.sdtw_align.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
+                               ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp,
+                               _vp, ctypes.c_size_t, _vp]
+    lib.sdtw_align.restype = ctypes.c_int
     lib.sdtw_znorm_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
     lib.sdtw_znorm_workspace_bytes.restype = ctypes.c_size_t
     lib.sdtw_znorm.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp]

@@ -162,6 +162,42 @@ def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
     return grad_queries, grad_reference
 
 
+def sdtw_align_workspace_bytes(h_query_lens, ref_len: int, ckpt_every: int) -> int:
+    h = _host_lens(h_query_lens)
+    return int(_lib.lib.sdtw_align_workspace_bytes(_hp(h), h.size, int(ref_len),
+                                                   int(ckpt_every)))
+
+
+def sdtw_align(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
+               reference: torch.Tensor, cost_kind: int, cost: torch.Tensor,
+               end_pos: torch.Tensor, ckpt: Optional[torch.Tensor], ckpt_every: int, *,
+               workspace_buf: Optional[torch.Tensor] = None,
+               stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Optimal alignment path of every query: (start_pos int64 [B], path_lo,
+    path_hi int32 packed like queries), the reference columns matched to each
+    query element; cost, end_pos and ckpt come from a checkpointed forward."""
+    h = _host_lens(h_query_lens)
+    _require_cuda("queries", queries, torch.float32)
+    _require_cuda("query_lens", query_lens, torch.int32)
+    _require_cuda("reference", reference, torch.float32)
+    _require_cuda("cost", cost, torch.float32)
+    _require_cuda("end_pos", end_pos, torch.int64)
+    dev = queries.device
+    start = torch.empty(h.size, dtype=torch.int64, device=dev)
+    lo = torch.empty(queries.numel(), dtype=torch.int32, device=dev)
+    hi = torch.empty(queries.numel(), dtype=torch.int32, device=dev)
+    need = sdtw_align_workspace_bytes(h, reference.numel(), ckpt_every)
+    if need == 0:
+        raise SdtwError(_lib.SDTW_ERR_INVALID_ARG, "sdtw_align_workspace_bytes")
+    if workspace_buf is None:
+        workspace_buf = workspace(need, dev)
+    st = _lib.lib.sdtw_align(
+        _dp(queries), _hp(h), _dp(query_lens), h.size, _dp(reference), reference.numel(),
+        int(cost_kind), _dp(cost), _dp(end_pos), _dp(ckpt), int(ckpt_every), _dp(start),
+        _dp(lo), _dp(hi), _dp(workspace_buf), workspace_buf.numel(), _stream(stream))
+    check(st, "sdtw_align")
+    return start, lo, hi
+
 def sdtw_znorm_workspace_bytes(h_lens) -> int:
     h = _host_lens(h_lens)
     return int(_lib.lib.sdtw_znorm_workspace_bytes(_hp(h), h.size))

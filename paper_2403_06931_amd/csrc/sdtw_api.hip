@@ -177,7 +177,9 @@ struct BwdLayout {
   int32_t nseg, slots, rounds;
 };
 
-BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t ckpt_every) {
+// with_grad = false (sdtw_align): no per-query reference partials.
+BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t ckpt_every,
+                     bool with_grad = true) {
   BwdLayout L{};
   L.nseg = (ckpt_every + sdtw::kDirSeg - 1) / sdtw::kDirSeg;
   const size_t words_per_slot =
@@ -200,7 +202,9 @@ BwdLayout bwd_layout(int32_t batch, int64_t total_len, int64_t ref_len, int32_t 
   L.row_hi = at;
   at = align_up(at + sizeof(int32_t) * (size_t)total_len, kAlign);
   L.part = at;
-  at = align_up(at + sizeof(float) * (size_t)batch * (size_t)row_stride_floats(ref_len), kAlign);
+  if (with_grad)
+    at = align_up(at + sizeof(float) * (size_t)batch * (size_t)row_stride_floats(ref_len),
+                  kAlign);
   L.codes = at;
   L.code_half = (int64_t)(words_per_slot * (size_t)slots);
   at = align_up(at + 2 * bytes_per_slot * (size_t)slots, kAlign);
@@ -239,6 +243,82 @@ ZLayout znorm_layout(const int32_t* h_lens, int32_t batch) {
 int launch(const void* fn, dim3 grid, dim3 block, void** args, hipStream_t stream) {
   hipError_t e = hipLaunchKernel(fn, grid, block, args, 0, stream);
   return e == hipSuccess ? SDTW_OK : SDTW_ERR_HIP;
+}
+
+// Parameters shared by the walk-back entry points (sdtw_backward, sdtw_align).
+sdtw::BwdParams bwd_params(const float* queries, const int32_t* query_lens, int32_t batch,
+                           const float* reference, int64_t ref_len, const float* cost,
+                           const int64_t* end_pos, const float* ckpt, int32_t ckpt_every,
+                           int64_t nck, int32_t nmax, const BwdLayout& L, void* workspace) {
+  char* ws = static_cast<char*>(workspace);
+  int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
+  sdtw::BwdParams p{};
+  p.queries = queries;
+  p.lens = query_lens;
+  p.offsets = offs;
+  p.reference = reference;
+  p.cost = cost;
+  p.end_pos = end_pos;
+  p.ckpt = ckpt;
+  p.ref_part = reinterpret_cast<float*>(ws + L.part);
+  p.path_lo = reinterpret_cast<int32_t*>(ws + L.lo);
+  p.row_lo = reinterpret_cast<int32_t*>(ws + L.row_lo);
+  p.row_hi = reinterpret_cast<int32_t*>(ws + L.row_hi);
+  p.state = reinterpret_cast<int32_t*>(ws + L.state);
+  p.codes = reinterpret_cast<uint32_t*>(ws + L.codes);
+  p.part_stride = row_stride_floats(ref_len);
+  p.batch = batch;
+  p.ref_len = (int32_t)ref_len;
+  p.ckpt_every = ckpt_every;
+  p.n_ckpt = (int32_t)nck;
+  p.nseg = L.nseg;
+  p.slots = L.slots;
+  p.max_rows = nmax;
+  p.round = 0;
+  p.code_half = L.code_half;
+  return p;
+}
+
+// The walk itself: offsets, walker state, round 0's recompute, then the
+// rounds (walk of round r beside the recompute of round r+1).  Leaves the
+// path bounds in p.row_lo, p.row_hi and p.path_lo.
+int bwd_walk(sdtw::BwdParams& p, const BwdLayout& L, const int32_t* query_lens, int32_t batch,
+             int32_t nmax, bool sq, hipStream_t stream) {
+  int64_t* offs = const_cast<int64_t*>(p.offsets);
+  int rc;
+  {
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
+                dim3(sdtw::kScanThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  {
+    void* args[] = {(void*)&p};
+    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_bwd_init_kernel),
+                dim3((batch + sdtw::kInitThreads - 1) / sdtw::kInitThreads),
+                dim3(sdtw::kInitThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  const size_t round_lds = sdtw::bwd_round_lds_bytes(nmax);
+  {
+    const void* dirs = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
+                          : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
+    void* args[] = {(void*)&p};
+    if (hipLaunchKernel(dirs, dim3(batch, L.slots), dim3(sdtw::kWave), args, round_lds,
+                        stream) != hipSuccess)
+      return SDTW_ERR_HIP;
+  }
+  const void* round_fn = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<0>)
+                            : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<1>);
+  for (int r = 0; r < L.rounds; ++r) {
+    p.round = r;
+    const int64_t grid = (int64_t)batch * (r + 1 < L.rounds ? 1 + L.slots : 1);
+    void* args[] = {(void*)&p};
+    if (hipLaunchKernel(round_fn, dim3((unsigned)grid), dim3(sdtw::kWave), args, round_lds,
+                        stream) != hipSuccess)
+      return SDTW_ERR_HIP;
+  }
+  return SDTW_OK;
 }
 
 }  // namespace
@@ -408,69 +488,13 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
   if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
 
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
-  char* ws = static_cast<char*>(workspace);
-  int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
-  sdtw::BwdParams p{};
-  p.queries = queries;
-  p.lens = query_lens;
-  p.offsets = offs;
-  p.reference = reference;
+  sdtw::BwdParams p = bwd_params(queries, query_lens, batch, reference, ref_len, cost, end_pos,
+                                 ckpt, ckpt_every, nck, nmax, L, workspace);
   p.grad_cost = grad_cost;
-  p.cost = cost;
-  p.end_pos = end_pos;
-  p.ckpt = ckpt;
   p.grad_q = grad_queries;
-  p.ref_part = reinterpret_cast<float*>(ws + L.part);
-  p.path_lo = reinterpret_cast<int32_t*>(ws + L.lo);
-  p.row_lo = reinterpret_cast<int32_t*>(ws + L.row_lo);
-  p.row_hi = reinterpret_cast<int32_t*>(ws + L.row_hi);
-  p.state = reinterpret_cast<int32_t*>(ws + L.state);
-  p.codes = reinterpret_cast<uint32_t*>(ws + L.codes);
-  p.part_stride = row_stride_floats(ref_len);
-  p.batch = batch;
-  p.ref_len = (int32_t)ref_len;
-  p.ckpt_every = ckpt_every;
-  p.n_ckpt = (int32_t)nck;
-  p.nseg = L.nseg;
-  p.slots = L.slots;
-  p.max_rows = nmax;
-  p.round = 0;
-  p.code_half = L.code_half;
-
-  int rc;
-  {
-    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
-    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
-                dim3(sdtw::kScanThreads), args, stream);
-    if (rc != SDTW_OK) return rc;
-  }
-  {
-    void* args[] = {(void*)&p};
-    rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_bwd_init_kernel),
-                dim3((batch + sdtw::kInitThreads - 1) / sdtw::kInitThreads),
-                dim3(sdtw::kInitThreads), args, stream);
-    if (rc != SDTW_OK) return rc;
-  }
   const bool sq = cost_kind == SDTW_COST_SQUARED;
-  const size_t round_lds = sdtw::bwd_round_lds_bytes(nmax);
-  {
-    const void* dirs = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
-                          : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
-    void* args[] = {(void*)&p};
-    if (hipLaunchKernel(dirs, dim3(batch, L.slots), dim3(sdtw::kWave), args, round_lds,
-                        stream) != hipSuccess)
-      return SDTW_ERR_HIP;
-  }
-  const void* round_fn = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<0>)
-                            : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<1>);
-  for (int r = 0; r < L.rounds; ++r) {
-    p.round = r;
-    const int64_t grid = (int64_t)batch * (r + 1 < L.rounds ? 1 + L.slots : 1);
-    void* args[] = {(void*)&p};
-    if (hipLaunchKernel(round_fn, dim3((unsigned)grid), dim3(sdtw::kWave), args, round_lds,
-                        stream) != hipSuccess)
-      return SDTW_ERR_HIP;
-  }
+  const int rc = bwd_walk(p, L, query_lens, batch, nmax, sq, stream);
+  if (rc != SDTW_OK) return rc;
   {
     const bool qlds = sdtw::bwd_grad_q_in_lds(nmax);
     const void* grad =
@@ -494,6 +518,54 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
     return launch(reinterpret_cast<const void*>(&sdtw::sdtw_ref_reduce_kernel), dim3(grid),
                   dim3(sdtw::kRefReduceThreads), args, stream);
   }
+}
+
+size_t sdtw_align_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
+                                  int32_t ckpt_every) {
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len) || ckpt_every < 1 ||
+      ckpt_every % kCkptQuantum != 0)
+    return 0;
+  if (nmax > sdtw::kDirMaxRows) return 0;
+  return bwd_layout(batch, total, ref_len, ckpt_every, false).total;
+}
+
+int sdtw_align(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
+               int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
+               const float* cost, const int64_t* end_pos, const float* ckpt, int32_t ckpt_every,
+               int64_t* start_pos, int32_t* path_lo, int32_t* path_hi, void* workspace,
+               size_t workspace_bytes, void* stream_ptr) {
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!queries || !query_lens || !reference || !cost || !end_pos || !start_pos || !path_lo ||
+      !path_hi || !workspace)
+    return SDTW_ERR_INVALID_ARG;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
+    return SDTW_ERR_INVALID_ARG;
+  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
+    return SDTW_ERR_INVALID_ARG;
+  if (ckpt_every < 1 || ckpt_every % kCkptQuantum != 0) return SDTW_ERR_INVALID_ARG;
+  const int64_t nck = n_ckpt_of(ref_len, ckpt_every);
+  if (nck > 0 && ckpt == nullptr) return SDTW_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  if (nmax > sdtw::kDirMaxRows) return SDTW_ERR_UNSUPPORTED;
+  const BwdLayout L = bwd_layout(batch, total, ref_len, ckpt_every, false);
+  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+  sdtw::BwdParams p = bwd_params(queries, query_lens, batch, reference, ref_len, cost, end_pos,
+                                 ckpt, ckpt_every, nck, nmax, L, workspace);
+  p.ref_part = nullptr;
+  p.row_lo = path_lo;                           // the walker writes the bounds in place
+  p.row_hi = path_hi;
+  const int rc = bwd_walk(p, L, query_lens, batch, nmax, cost_kind == SDTW_COST_SQUARED, stream);
+  if (rc != SDTW_OK) return rc;
+  const int32_t* lo = p.path_lo;
+  void* args[] = {(void*)&lo, (void*)&batch, (void*)&start_pos};
+  return launch(reinterpret_cast<const void*>(&sdtw::sdtw_align_start_kernel),
+                dim3((batch + sdtw::kInitThreads - 1) / sdtw::kInitThreads),
+                dim3(sdtw::kInitThreads), args, stream);
 }
 
 size_t sdtw_znorm_workspace_bytes(const int32_t* h_lens, int32_t batch) {

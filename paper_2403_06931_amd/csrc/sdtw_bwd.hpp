@@ -136,8 +136,14 @@ __global__ __launch_bounds__(kInitThreads) void sdtw_bwd_init_kernel(const BwdPa
   p.row_hi[p.offsets[b] + n - 1] = e;
 }
 
-// One row step of the direction recompute.  MASKED: some lanes are outside
-// rows 1..nrows and keep their state (row 0 before they start).
+// Start of each query's path (the column of its row-1 cell), widened to the
+// ABI's index type.
+__global__ __launch_bounds__(kInitThreads) void sdtw_align_start_kernel(
+    const int32_t* __restrict__ path_lo, int32_t batch, int64_t* __restrict__ start_pos) {
+  const int b = blockIdx.x * kInitThreads + threadIdx.x;
+  if (b < batch) start_pos[b] = path_lo[b];
+}
+
 // Lane 0's inputs of step g (row g+1): the segment's left column and the
 // query value, read one step ahead of their use.
 __device__ __forceinline__ void dirs_inputs(int g, int nrows, const float* lq, const float* ledge,
@@ -147,6 +153,8 @@ __device__ __forceinline__ void dirs_inputs(int g, int nrows, const float* lq, c
   iq = lq[gi];
 }
 
+// One row step of the direction recompute.  MASKED: some lanes are outside
+// rows 1..nrows and keep their state (row 0 before they start).
 template <int KIND, bool MASKED>
 __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, float il, float iq,
                                           float* ledge, const float (&rv)[kDirCols],

@@ -178,3 +178,36 @@ def test_znorm_workspace_sizes(L):
     # 16 bytes of binary64 partials per 4,096-element chunk at least
     assert b >= 16 * (2_000_000 // 4096)
     assert P.sdtw_znorm_workspace_bytes(np.array([10, 0], np.int32)) == 0
+
+
+def _al(L, lens, ref_len=100, kind=0, every=64, ckpt=FAKE, ws_bytes=1 << 40, **ptrs):
+    h = np.ascontiguousarray(lens, dtype=np.int32)
+    a = dict(q=FAKE, dlens=FAKE, r=FAKE, c=FAKE, e=FAKE, s=FAKE, lo=FAKE, hi=FAKE, ws=FAKE)
+    a.update(ptrs)
+    return L.lib.sdtw_align(_vp(a["q"]), _vp(h.ctypes.data), _vp(a["dlens"]), h.size,
+                            _vp(a["r"]), ref_len, kind, _vp(a["c"]), _vp(a["e"]), _vp(ckpt),
+                            every, _vp(a["s"]), _vp(a["lo"]), _vp(a["hi"]), _vp(a["ws"]),
+                            ws_bytes, _vp(0))
+
+
+def test_align_rejects_invalid_arguments(L):
+    E = L.SDTW_ERR_INVALID_ARG
+    for name in ("q", "dlens", "r", "c", "e", "s", "lo", "hi", "ws"):
+        assert _al(L, [3, 4], **{name: 0}) == E, name
+    assert _al(L, [3, 0]) == E
+    assert _al(L, [3, 4], kind=2) == E
+    assert _al(L, [3, 4], every=40) == E
+    assert _al(L, [3, 4], ref_len=1000, ckpt=0) == E
+    assert _al(L, [3, 4], ws=FAKE + 64) == E
+    assert _al(L, [3, 4], ws_bytes=100) == L.SDTW_ERR_WORKSPACE
+    assert _al(L, [8193]) == L.SDTW_ERR_UNSUPPORTED
+
+
+def test_align_workspace_smaller_than_backward(L):
+    import paper_2403_06931_amd as P
+    lens = np.array([1000] * 256, np.int32)
+    a = P.sdtw_align_workspace_bytes(lens, 50000, 1024)
+    b = P.sdtw_backward_workspace_bytes(lens, 50000, 1024)
+    # no per-query reference partials (256 x 50,000 floats)
+    assert 0 < a and a + 256 * 50000 * 4 <= b
+    assert P.sdtw_align_workspace_bytes(np.array([8193], np.int32), 100, 64) == 0
