@@ -41,6 +41,10 @@ def _load():
                                     ctypes.c_int, _f32p, _i64p, ctypes.c_int]
     lib.oracle_sdtw_f64.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
                                     ctypes.c_int, _f64p, _i64p, ctypes.c_int]
+    lib.oracle_sdtw_f16.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
+                                    ctypes.c_int, _f32p, _i64p, ctypes.c_int]
+    lib.oracle_round_f16.argtypes = [ctypes.c_double]
+    lib.oracle_round_f16.restype = ctypes.c_double
     lib.oracle_sdtw_last_row_f32.argtypes = [_f32p, ctypes.c_int32, _f32p, ctypes.c_int64,
                                              ctypes.c_int, _f32p]
     lib.oracle_dtw_f32.argtypes = [_f32p, ctypes.c_int32, _f32p, ctypes.c_int64,
@@ -52,7 +56,7 @@ def _load():
                                          ctypes.c_int, _i64p, _i64p]
     lib.oracle_sdtw_path_f32.restype = ctypes.c_int64
     lib.oracle_max_threads.restype = ctypes.c_int
-    for name in ("oracle_sdtw_f32", "oracle_sdtw_f64", "oracle_sdtw_last_row_f32",
+    for name in ("oracle_sdtw_f32", "oracle_sdtw_f64", "oracle_sdtw_f16", "oracle_sdtw_last_row_f32",
                  "oracle_dtw_f32", "oracle_sdtw_grad_f32"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -106,6 +110,27 @@ def sdtw_f64(queries, lens, reference, kind=SQUARED, nthreads=0):
     if rc != 0:
         raise ValueError("oracle_sdtw_f64 rejected its arguments")
     return cost, end
+
+
+def sdtw_f16(queries, lens, reference, kind=SQUARED, nthreads=0):
+    """Batched sDTW in binary16 arithmetic (inputs and every operation rounded
+    to binary16) -> (cost float32 [B] holding binary16 values, end_pos int64 [B])."""
+    lib = _load()
+    q = _f32(queries).ravel()
+    lens = _lens(q, lens)
+    r = _f32(reference).ravel()
+    cost = np.empty(lens.size, np.float32)
+    end = np.empty(lens.size, np.int64)
+    rc = lib.oracle_sdtw_f16(_p(q, _f32p), _p(lens, _i32p), lens.size, _p(r, _f32p), r.size,
+                             int(kind), _p(cost, _f32p), _p(end, _i64p), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_sdtw_f16 rejected its arguments")
+    return cost, end
+
+
+def round_f16(x: float) -> float:
+    """The oracle's own rounding to the nearest binary16 value (ties to even)."""
+    return float(_load().oracle_round_f16(float(x)))
 
 
 def last_row_f32(query, reference, kind=SQUARED):

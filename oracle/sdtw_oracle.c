@@ -146,6 +146,64 @@ static void sdtw_one_f64(const float *q, int64_t n, const float *r, int64_t m,
     *end_pos = arg - 1;
 }
 
+/* ------------------------------------------------------------------ */
+/* Binary16 (the paper's own precision, Section 5.2 and Section 8):     */
+/* every input and every operation result is rounded to the nearest     */
+/* binary16 value, ties to even.  Values are carried in doubles: the    */
+/* difference, product or sum of two binary16 numbers is exact in       */
+/* binary64 (at most 41 significant bits), so one rounding per          */
+/* operation gives the correctly rounded binary16 result.               */
+/* ------------------------------------------------------------------ */
+
+/* Nearest binary16 value of x (ties to even), as a double.  binary16 has
+ * an 11-bit significand, normal exponents -14..15 and subnormal spacing
+ * 2^-24; magnitudes from 65520 (the midpoint between the largest finite
+ * value 65504 and 2^16, which rounds to the even side) up overflow to inf. */
+double oracle_round_f16(double x)
+{
+    if (x != x || x == 0.0 || isinf(x)) return x;
+    int e;
+    frexp(fabs(x), &e);                  /* |x| = f * 2^e, f in [0.5, 1) */
+    int ex = e - 1;                      /* |x| in [2^ex, 2^(ex+1)) */
+    if (ex < -14) ex = -14;              /* subnormal range: fixed spacing */
+    double quantum = ldexp(1.0, ex - 10);
+    double r = nearbyint(x / quantum) * quantum;   /* exact scaling, RNE */
+    if (fabs(r) > 65504.0) return copysign(INFINITY, x);
+    return r;
+}
+
+static double local_cost_f16(double q, double r, int kind)
+{
+    double t = oracle_round_f16(q - r);
+    if (kind == ORACLE_SQUARED) return oracle_round_f16(t * t);
+    return fabs(t);
+}
+
+/* One query in binary16 arithmetic (values held as doubles). */
+static void sdtw_one_f16(const float *q, int64_t n, const float *r, int64_t m,
+                         int kind, double *prev, double *cur,
+                         float *cost, int64_t *end_pos)
+{
+    for (int64_t j = 0; j <= m; ++j) prev[j] = 0.0;
+    for (int64_t i = 1; i <= n; ++i) {
+        cur[0] = INFINITY;
+        double qi = oracle_round_f16((double)q[i - 1]);
+        for (int64_t j = 1; j <= m; ++j) {
+            double c = local_cost_f16(qi, oracle_round_f16((double)r[j - 1]), kind);
+            double mn = min3_f64(prev[j], cur[j - 1], prev[j - 1]);
+            cur[j] = oracle_round_f16(mn + c);
+        }
+        double *t = prev; prev = cur; cur = t;
+    }
+    double best = prev[1];
+    int64_t arg = 1;
+    for (int64_t j = 2; j <= m; ++j) {
+        if (prev[j] < best) { best = prev[j]; arg = j; }
+    }
+    *cost = (float)best;                 /* a binary16 value: exact in binary32 */
+    *end_pos = arg - 1;
+}
+
 /* Query b of a packed batch starts at the sum of the lengths before it. */
 static int64_t *make_offsets(const int32_t *lens, int32_t batch)
 {
@@ -231,6 +289,38 @@ int oracle_sdtw_f64(const float *queries, const int32_t *lens, int32_t batch,
 #pragma omp for schedule(dynamic, 1)
             for (int32_t b = 0; b < batch; ++b)
                 sdtw_one_f64(queries + off[b], lens[b], ref, ref_len, kind,
+                             prev, cur, &cost[b], &end_pos[b]);
+        }
+        free(prev);
+        free(cur);
+    }
+    free(off);
+    return failed ? -1 : 0;
+}
+
+/* Batched binary16 sDTW (inputs rounded to binary16; costs returned as the
+ * binary32 values of the binary16 results). */
+int oracle_sdtw_f16(const float *queries, const int32_t *lens, int32_t batch,
+                    const float *ref, int64_t ref_len, int kind,
+                    float *cost, int64_t *end_pos, int nthreads)
+{
+    if (batch < 1 || ref_len < 1 || (kind != 0 && kind != 1)) return -1;
+    for (int32_t b = 0; b < batch; ++b) if (lens[b] < 1) return -1;
+    int64_t *off = make_offsets(lens, batch);
+    if (!off) return -1;
+    int failed = 0;
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        double *prev = (double *)malloc(sizeof(double) * (size_t)(ref_len + 1));
+        double *cur = (double *)malloc(sizeof(double) * (size_t)(ref_len + 1));
+        if (!prev || !cur) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int32_t b = 0; b < batch; ++b)
+                sdtw_one_f16(queries + off[b], lens[b], ref, ref_len, kind,
                              prev, cur, &cost[b], &end_pos[b]);
         }
         free(prev);
