@@ -19,6 +19,10 @@ Prints ONE JSON line.  Beside the headline value it reports:
                 loop of plain launches over 16 length buckets;
   fwd_bwd       forward with checkpoints plus the walk-back gradient
                 (256 x 1,000 vs 50,000);
+  f16           the same workload in binary16 arithmetic (two queries per
+                packed value), against the packed-FP16 issue rate: gfx950
+                never dual-issues packed (VOP3P) instructions, so its roofline
+                is 256 CUs x 64 lanes x 2.4 GHz / 2.5 instructions per cell;
   znorm         the batch z-normaliser that prepares the inputs, against
                 the 8 TB/s HBM roofline (8 algorithmic bytes per sample:
                 one read, one write).
@@ -240,6 +244,40 @@ def fwd_bwd_leg(P, torch, steps, warmup):
 HBM_PEAK_GBS = 8000.0
 
 
+def f16_leg(P, torch, steps, warmup):
+    """sdtw_forward_f16 on the headline workload; the tile variant is picked
+    by timing every compiled variant once (two calls each)."""
+    import workloads
+    w = workloads.make_config(1)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    ws = P.workspace(P.sdtw_forward_f16_workspace_bytes(w.lens, w.ref_len), dev)
+    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    times = {}
+    for v in range(P.sdtw_variant_count()):
+        def run(v=v):
+            P.sdtw_forward_f16(q, w.lens, l, r, 0, cost=cost, end_pos=end, variant=v,
+                               workspace_buf=ws)
+        times[v] = time_steps(run, 1, 1, torch)[1]
+    best = min(times, key=times.get)
+
+    def step():
+        P.sdtw_forward_f16(q, w.lens, l, r, 0, cost=cost, end_pos=end, variant=best,
+                           workspace_buf=ws)
+    wall_ms, ev_ms = time_steps(step, steps, warmup, torch)
+    peak = valu_peak_gcups(2.5, lanes=64)
+    return {"workload": w.name, "dtype": "f16", "cells": w.cells, "ms_per_step": wall_ms,
+            "gcups": w.cells / (wall_ms * 1e6), "kernel_ms": ev_ms,
+            "variant": P.sdtw_variant_info(best),
+            "roofline": {"bound": "alu", "achieved": w.cells / (ev_ms * 1e6), "peak": peak,
+                         "unit": "GCUPS", "frac": w.cells / (ev_ms * 1e6) / peak,
+                         "peak_basis": "256 CU x 64 lanes/clk (packed FP16 is never "
+                                       "dual-issued) x 2.4 GHz / 2.5 VALU ops per cell"}}
+
+
 def znorm_leg(P, torch, steps, warmup):
     """sdtw_znorm on raw (unnormalised) series of the evaluation's shapes."""
     import numpy as np
@@ -372,6 +410,7 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(P, torch, steps=3, warmup=1)
         out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1)
+        out["f16"] = f16_leg(P, torch, steps=5, warmup=1)
         out["znorm"] = znorm_leg(P, torch, steps=20, warmup=3)
     print(json.dumps(out), flush=True)
 

@@ -184,6 +184,28 @@ SDTW_API int sdtw_backward(const float *queries, const int32_t *h_query_lens,
                   void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * sDTW in binary16, the paper's own precision (Section 5.2 converts queries
+ * and reference to half precision and computes on packed pairs; Section 8).
+ * Same operation and outputs as sdtw_forward, with every input and every
+ * operation (t = q - r, t*t or |t|, min + c) rounded to nearest-even
+ * binary16, subnormals kept; values past 65504 become +inf.  cost holds the
+ * binary16 result exactly as a float32.  Queries are processed in pairs
+ * (2i, 2i+1), one per half of each packed value, so each pair must have
+ * equal lengths (else SDTW_ERR_UNSUPPORTED); an odd batch's last query runs
+ * alone.  variant: as for sdtw_forward (-1 = library choice); no
+ * checkpoints, no persistent form.  workspace:
+ * sdtw_forward_f16_workspace_bytes(...) bytes, 256-byte aligned.
+ */
+SDTW_API size_t sdtw_forward_f16_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
+                                                 int64_t ref_len);
+
+SDTW_API int sdtw_forward_f16(const float *queries, const int32_t *h_query_lens,
+                              const int32_t *query_lens, int32_t batch,
+                              const float *reference, int64_t ref_len, int32_t cost_kind,
+                              float *cost, int64_t *end_pos, int32_t variant,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Alignment path of every query (paper: Section 2, the walk back from the
  * minimum of the last row that recovers the optimal warping path), from the
  * outputs of an sdtw_forward call made with SDTW_F_CHECKPOINT.  The walk

@@ -62,6 +62,12 @@ def _load():
                                   ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
                                   _vp, ctypes.c_size_t, _vp]
     lib.sdtw_backward.restype = ctypes.c_int
+    lib.sdtw_forward_f16_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
+    lib.sdtw_forward_f16_workspace_bytes.restype = ctypes.c_size_t
+    lib.sdtw_forward_f16.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
+                                     ctypes.c_int32, _vp, _vp, ctypes.c_int32, _vp,
+                                     ctypes.c_size_t, _vp]
+    lib.sdtw_forward_f16.restype = ctypes.c_int
     lib.sdtw_align_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64,
                                                ctypes.c_int32]
     lib.sdtw_align_workspace_bytes.restype = ctypes.c_size_t

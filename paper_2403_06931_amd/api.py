@@ -162,6 +162,42 @@ def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
     return grad_queries, grad_reference
 
 
+def sdtw_forward_f16_workspace_bytes(h_query_lens, ref_len: int) -> int:
+    h = _host_lens(h_query_lens)
+    return int(_lib.lib.sdtw_forward_f16_workspace_bytes(_hp(h), h.size, int(ref_len)))
+
+
+def sdtw_forward_f16(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
+                     reference: torch.Tensor, cost_kind: int = SDTW_COST_SQUARED, *,
+                     cost: Optional[torch.Tensor] = None,
+                     end_pos: Optional[torch.Tensor] = None, variant: int = -1,
+                     workspace_buf: Optional[torch.Tensor] = None,
+                     stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """sDTW in binary16 arithmetic on float32 inputs: (cost float32 [B] holding
+    binary16 values, end_pos int64 [B]).  Queries 2i and 2i+1 must have equal
+    lengths."""
+    h = _host_lens(h_query_lens)
+    _require_cuda("queries", queries, torch.float32)
+    _require_cuda("query_lens", query_lens, torch.int32)
+    _require_cuda("reference", reference, torch.float32)
+    dev = queries.device
+    b = h.size
+    if cost is None:
+        cost = torch.empty(b, dtype=torch.float32, device=dev)
+    if end_pos is None:
+        end_pos = torch.empty(b, dtype=torch.int64, device=dev)
+    need = sdtw_forward_f16_workspace_bytes(h, reference.numel())
+    if need == 0:
+        raise SdtwError(_lib.SDTW_ERR_UNSUPPORTED, "sdtw_forward_f16_workspace_bytes")
+    if workspace_buf is None:
+        workspace_buf = workspace(need, dev)
+    st = _lib.lib.sdtw_forward_f16(
+        _dp(queries), _hp(h), _dp(query_lens), b, _dp(reference), reference.numel(),
+        int(cost_kind), _dp(cost), _dp(end_pos), int(variant), _dp(workspace_buf),
+        workspace_buf.numel(), _stream(stream))
+    check(st, "sdtw_forward_f16")
+    return cost, end_pos
+
 def sdtw_align_workspace_bytes(h_query_lens, ref_len: int, ckpt_every: int) -> int:
     h = _host_lens(h_query_lens)
     return int(_lib.lib.sdtw_align_workspace_bytes(_hp(h), h.size, int(ref_len),

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "sdtw.h"
 #include "sdtw_argmin.hpp"
@@ -321,6 +322,18 @@ int bwd_walk(sdtw::BwdParams& p, const BwdLayout& L, const int32_t* query_lens, 
   return SDTW_OK;
 }
 
+// Binary16 form: queries go in pairs (2i, 2i+1) of equal length, one per
+// half of each packed value; returns the pair lengths, or an empty vector if
+// a pair's lengths differ.
+std::vector<int32_t> f16_pair_lens(const int32_t* h_lens, int32_t batch) {
+  std::vector<int32_t> pl((size_t)(batch + 1) / 2);
+  for (int32_t i = 0; 2 * i < batch; ++i) {
+    if (2 * i + 1 < batch && h_lens[2 * i + 1] != h_lens[2 * i]) return {};
+    pl[(size_t)i] = h_lens[2 * i];
+  }
+  return pl;
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -451,6 +464,62 @@ int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_
   }
   void* args[] = {(void*)&p};
   return launch(v.plain[cost_kind][ck], dim3(batch), dim3(64 * v.W), args, stream);
+}
+
+size_t sdtw_forward_f16_workspace_bytes(const int32_t* h_query_lens, int32_t batch,
+                                        int64_t ref_len) {
+  if (!lens_ok(h_query_lens, batch, nullptr, nullptr) || !ref_ok(ref_len)) return 0;
+  if (f16_pair_lens(h_query_lens, batch).empty()) return 0;
+  return fwd_layout(batch, ref_len, 0, (batch + 1) / 2).total;
+}
+
+int sdtw_forward_f16(const float* queries, const int32_t* h_query_lens,
+                     const int32_t* query_lens, int32_t batch, const float* reference,
+                     int64_t ref_len, int32_t cost_kind, float* cost, int64_t* end_pos,
+                     int32_t variant_id, void* workspace, size_t workspace_bytes,
+                     void* stream_ptr) {
+  if (!queries || !query_lens || !reference || !cost || !end_pos || !workspace)
+    return SDTW_ERR_INVALID_ARG;
+  if (!lens_ok(h_query_lens, batch, nullptr, nullptr) || !ref_ok(ref_len))
+    return SDTW_ERR_INVALID_ARG;
+  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
+    return SDTW_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  const std::vector<int32_t> pl = f16_pair_lens(h_query_lens, batch);
+  if (pl.empty()) return SDTW_ERR_UNSUPPORTED;
+  if (variant_id < -1 || variant_id >= variant_count()) return SDTW_ERR_UNSUPPORTED;
+  const int32_t pairs = (batch + 1) / 2;
+  const FwdLayout L = fwd_layout(batch, ref_len, 0, pairs);
+  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+  const int vid = variant_id >= 0 ? variant_id
+                                  : pick_variant(pl.data(), pairs, ref_len, 0, device_cus());
+  const Variant& v = variant(vid);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+  char* ws = static_cast<char*>(workspace);
+
+  FwdParams p{};
+  p.queries = queries;
+  p.lens = query_lens;
+  p.reference = reference;
+  p.rowbuf = reinterpret_cast<float*>(ws + L.rowbuf);
+  p.cost = cost;
+  p.end_pos = end_pos;
+  p.ckpt = nullptr;
+  p.row_stride = row_stride_floats(ref_len);
+  p.batch = batch;
+  p.ref_len = (int32_t)ref_len;
+  if (batch > kInKernelOffsetBatch) {
+    int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
+                    dim3(sdtw::kScanThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+    p.offsets = offs;
+  } else {
+    p.offsets = nullptr;            // each workgroup sums the lengths before its pair
+  }
+  void* args[] = {(void*)&p};
+  return launch(v.half[cost_kind], dim3(pairs), dim3(64 * v.W), args, stream);
 }
 
 size_t sdtw_backward_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,

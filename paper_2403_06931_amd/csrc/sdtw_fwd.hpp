@@ -42,6 +42,7 @@
 
 #include "sdtw_argmin.hpp"
 #include "sdtw_common.hpp"
+#include "sdtw_value.hpp"
 
 namespace sdtw {
 
@@ -92,21 +93,22 @@ struct FwdShape {
 // Stage the reference tiles [tile0, tile0 + KS) and the wave-0 top boundary
 // (zeros on the first pass, the previous pass's last row after it) from
 // global memory into registers; commit them to the LDS rings later.
-template <int R, int T, int W, int KS, int XL>
+template <int R, int T, int W, int KS, int XL, typename V = float>
 struct Stager {
   using S = FwdShape<R, T, W, KS, XL>;
   static constexpr int PER = (S::CHUNK + S::THREADS - 1) / S::THREADS;
   float ref[PER];
-  float top[PER];
+  V top[PER];
 
   __device__ __forceinline__ void load(const float* __restrict__ reference, int ref_len,
-                                       const float* __restrict__ prev_row, int row_len,
+                                       const V* __restrict__ prev_row, int row_len,
                                        int tile0, int tid) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + u * S::THREADS;
       const int j = tile0 * T + e;
-      float rv = 0.0f, tv = 0.0f;
+      float rv = 0.0f;
+      V tv = Val<V>::zero();
       if (e < S::CHUNK) {
         if (j < ref_len) rv = reference[j];
         if (prev_row != nullptr && j < row_len) tv = prev_row[j];
@@ -116,13 +118,13 @@ struct Stager {
     }
   }
 
-  __device__ __forceinline__ void commit(float* s_ref, float* s_hand0, int tile0, int tid) const {
+  __device__ __forceinline__ void commit(V* s_ref, V* s_hand0, int tile0, int tid) const {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + u * S::THREADS;
       if (e < S::CHUNK) {
         const int j = tile0 * T + e;
-        s_ref[j & (S::SR * T - 1)] = ref[u];
+        s_ref[j & (S::SR * T - 1)] = Val<V>::ref(ref[u]);
         s_hand0[j & (S::SH * T - 1)] = top[u];
       }
     }
@@ -141,17 +143,18 @@ __device__ __forceinline__ int64_t uniform_i64(unsigned long long v) {
   return (int64_t)(((unsigned long long)hi << 32) | lo);
 }
 
-// Per-lane DP state of one pass.
-template <int R, int T>
+// Per-lane DP state of one pass (V: one binary32 query per lane row, or two
+// binary16 queries packed in halves).
+template <int R, int T, typename V = float>
 struct LaneState {
-  float qv[R];     // query values of the lane's rows
-  float dl[R];     // DP values of the lane's rows at the last column done
-  float bot[T];    // the lane's bottom row over the last tile (feeds lane + 1)
-  float corner;    // top boundary at the column before the current tile
+  V qv[R];         // query values of the lane's rows
+  V dl[R];         // DP values of the lane's rows at the last column done
+  V bot[T];        // the lane's bottom row over the last tile (feeds lane + 1)
+  V corner;        // top boundary at the column before the current tile
   int ck_h;        // step at which the lane reaches its next checkpoint column
   int ck_k;        // index of that checkpoint (0-based)
   float ckv[R];    // the lane's rows at the last checkpoint column reached
-  ValIdx am;       // running (minimum, first minimiser) of row N (its wavefront)
+  ValIdx am[Val<V>::N];   // running (minimum, first minimiser) of row N, per query
 };
 
 // Uniform (per wavefront) geometry of one pass.
@@ -195,31 +198,60 @@ __device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& 
 // the wavefront holding the row to store and that row's register index.
 // `top` is the block's top boundary: the previous lane's bottom row over this
 // tile (for lane 0, the previous wave's, or the top boundary of the pass).
-template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK>
-__device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
-                                         const PassGeom& G, const float (&rv)[T],
-                                         const float (&top)[T], int g, float* s_hand,
-                                         float* s_slot) {
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK, typename V>
+__device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>& L,
+                                         const PassGeom& G, const V (&rv)[T],
+                                         const V (&top)[T], int g, V* s_hand, V* s_slot) {
   using S = FwdShape<R, T, W, KS, XL>;
-  float up[T];
+  V up[T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) up[t] = XL ? top[t] : wave_shr1(top[t], L.bot[t]);
-  float upleft = L.corner;                      // D(row-1, first col - 1)
+  for (int t = 0; t < T; ++t) up[t] = XL ? top[t] : Val<V>::shr1(top[t], L.bot[t]);
+  V upleft = L.corner;                          // D(row-1, first col - 1)
   L.corner = up[T - 1];
   const int tau_out = g - G.out_delay;
   const bool do_out = OUTK >= 0 && tau_out >= 0 && tau_out < G.ntiles;
+  if constexpr (Val<V>::N == 2) {
+    // Packed binary16: anti-diagonal order.  gfx950 needs a wait state
+    // between dependent packed instructions; cells (k, t) and (k+1, t-1)
+    // are independent, so this order puts independent work between them.
+    V D[R][T];
+#pragma unroll
+    for (int d = 0; d < R + T - 1; ++d) {
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        const int t = d - k;
+        if (t < 0 || t >= T) continue;
+        const V u = k == 0 ? up[t] : D[k - 1][t];
+        const V lf = t == 0 ? L.dl[k] : D[k][t - 1];
+        const V dg = t == 0 ? (k == 0 ? upleft : L.dl[k - 1]) : (k == 0 ? up[t - 1] : D[k - 1][t - 1]);
+        const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t]);
+        D[k][t] = Val<V>::add(Val<V>::min3(u, lf, dg), c);
+      }
+    }
+    if constexpr (OUTK >= 0) {
+      if (do_out && G.lane == G.out_lane) {
+        V* dst = reinterpret_cast<V*>(G.s_out) + (g & (KS - 1)) * T;
+#pragma unroll
+        for (int t = 0; t < T; ++t) dst[t] = D[OUTK][t];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) L.dl[k] = D[k][T - 1];
+#pragma unroll
+    for (int t = 0; t < T; ++t) up[t] = D[R - 1][t];
+  } else {
   // The block row by row (measured faster on gfx950 than anti-diagonal
   // order, which the compiler schedules worse for dual issue).
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    float left = L.dl[k];
-    float diag = upleft;
-    float cur[T];
+    V left = L.dl[k];
+    V diag = upleft;
+    V cur[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const float c = local_cost<KIND>(L.qv[k], rv[t]);
-      const float mn = min3(up[t], left, diag);
-      cur[t] = mn + c;
+      const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t]);
+      const V mn = Val<V>::min3(up[t], left, diag);
+      cur[t] = Val<V>::add(mn, c);
       diag = up[t];
       left = cur[t];
     }
@@ -230,7 +262,7 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
         // to LDS only: at the interval's end the wave folds it (row N) or
         // copies it to the row buffer (keeping a global store out of the
         // step, whose LDS waits would otherwise cover it)
-        float* dst = G.s_out + (g & (KS - 1)) * T;
+        V* dst = reinterpret_cast<V*>(G.s_out) + (g & (KS - 1)) * T;
 #pragma unroll
         for (int t = 0; t < T; ++t) dst[t] = cur[t];
       }
@@ -238,20 +270,21 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
 #pragma unroll
     for (int t = 0; t < T; ++t) up[t] = cur[t];
   }
+  }
 #pragma unroll
   for (int t = 0; t < T; ++t) L.bot[t] = up[t];
 
   if constexpr (XL) {
     // the bottom row feeds lane l+1 (its slot is read during the next step,
     // before this lane overwrites it at the end of that step)
-    float* sout = s_slot + (G.wave * kWave + G.lane) * T;
+    V* sout = s_slot + (G.wave * kWave + G.lane) * T;
 #pragma unroll
     for (int t = 0; t < T; ++t) sout[t] = L.bot[t];
   }
 
   // lane 63 hands its bottom row to the next wave
   if (G.wave + 1 < W && G.lane == kWave - 1) {
-    float* hout = s_hand + (G.wave + 1) * S::SH * T + ((g - G.lane63_delay) & (S::SH - 1)) * T;
+    V* hout = s_hand + (G.wave + 1) * S::SH * T + ((g - G.lane63_delay) & (S::SH - 1)) * T;
 #pragma unroll
     for (int t = 0; t < T; ++t) hout[t] = L.bot[t];
   }
@@ -276,14 +309,13 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T>& L,
 // (lane 0: this wave's handoff ring; with XL the others read lane l-1's
 // slot, written at the end of step g-2; without, every lane reads the ring
 // and fwd_step shifts the bottom rows instead).
-template <int R, int T, int W, int KS, int XL>
-__device__ __forceinline__ void step_inputs(float (&rv)[T], float (&top)[T], int g,
-                                            const PassGeom& G, const float* s_ref,
-                                            const float* s_hand, const float* s_slot) {
+template <int R, int T, int W, int KS, int XL, typename V>
+__device__ __forceinline__ void step_inputs(V (&rv)[T], V (&top)[T], int g, const PassGeom& G,
+                                            const V* s_ref, const V* s_hand, const V* s_slot) {
   using S = FwdShape<R, T, W, KS, XL>;
-  const float* rin = s_ref + ((g - G.my_delay) & (S::SR - 1)) * T;
-  const float* hin = s_hand + G.wave * S::SH * T + ((g - G.lane0_delay) & (S::SH - 1)) * T;
-  const float* tin = (XL && G.lane != 0) ? s_slot + (G.wave * kWave + G.lane - 1) * T : hin;
+  const V* rin = s_ref + ((g - G.my_delay) & (S::SR - 1)) * T;
+  const V* hin = s_hand + G.wave * S::SH * T + ((g - G.lane0_delay) & (S::SH - 1)) * T;
+  const V* tin = (XL && G.lane != 0) ? s_slot + (G.wave * kWave + G.lane - 1) * T : hin;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     rv[t] = rin[t];
@@ -293,17 +325,26 @@ __device__ __forceinline__ void step_inputs(float (&rv)[T], float (&top)[T], int
 
 // Fold the row-N values the out lane wrote during interval `it` (tiles
 // it*KS + s - out_delay, s < KS) into this lane's running (minimum, first
-// minimiser).  A lane sees the columns in increasing order, so a strict
-// comparison keeps the first minimiser.
-template <int T, int KS>
-__device__ __forceinline__ void out_fold(ValIdx& am, const PassGeom& G, int it, int ref_len) {
+// minimiser), one per query of the value.  A lane sees the columns in
+// increasing order, so a strict comparison keeps the first minimiser; the
+// index comparison only matters for a row that is +inf throughout (an
+// overflow), whose first column is then reported.
+template <int T, int KS, typename V>
+__device__ __forceinline__ void out_fold(ValIdx (&am)[Val<V>::N], const PassGeom& G, int it,
+                                         int ref_len) {
+  const V* s_out = reinterpret_cast<const V*>(G.s_out);
   for (int e = G.lane; e < KS * T; e += kWave) {
     const int tau = it * KS + e / T - G.out_delay;
     const int j = tau * T + e % T;
-    const float v = G.s_out[e];
-    if (tau >= 0 && tau < G.ntiles && j < ref_len && v < am.v) {
-      am.v = v;
-      am.i = j;
+    const V x = s_out[e];
+    const bool in = tau >= 0 && tau < G.ntiles && j < ref_len;
+#pragma unroll
+    for (int h = 0; h < Val<V>::N; ++h) {
+      const float v = Val<V>::half(x, h);
+      if (in && (v < am[h].v || (v == am[h].v && j < am[h].i))) {
+        am[h].v = v;
+        am[h].i = j;
+      }
     }
   }
 }
@@ -320,23 +361,23 @@ __device__ __forceinline__ void out_copy(const PassGeom& G, int it) {
 
 // All barrier intervals of one pass.  The LDS inputs of step g+1 are read
 // while step g computes (two register sets, the step loop unrolled by two).
-template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK>
-__device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
-                                         const PassGeom& G, const float* prev_row,
-                                         float* s_ref, float* s_hand, float* s_slot) {
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK, typename V>
+__device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>& L,
+                                         const PassGeom& G, const V* prev_row, V* s_ref,
+                                         V* s_hand, V* s_slot) {
   const int tid = threadIdx.x;
-  float rvA[T], injA[T], rvB[T], injB[T];
+  V rvA[T], injA[T], rvB[T], injB[T];
   step_inputs<R, T, W, KS, XL>(rvA, injA, 0, G, s_ref, s_hand, s_slot);
   for (int it = 0; it < G.nint; ++it) {
-    Stager<R, T, W, KS, XL> st;
+    Stager<R, T, W, KS, XL, V> st;
     st.load(p.reference, p.ref_len, prev_row, G.ntiles * T, (it + 2) * KS, tid);
 #pragma unroll 1
     for (int s = 0; s < KS; s += 2) {
       const int g = it * KS + s;
       step_inputs<R, T, W, KS, XL>(rvB, injB, g + 1, G, s_ref, s_hand, s_slot);
-      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK>(p, L, G, rvA, injA, g, s_hand, s_slot);
+      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvA, injA, g, s_hand, s_slot);
       step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
-      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
+      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
     }
     // The stager's commit waits for its loads with a vmcnt wait, which on
     // gfx950 also covers every store issued before it; the interval's global
@@ -348,7 +389,7 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
     }
     if constexpr (OUTK >= 0) {
       if (G.final_pass) {
-        out_fold<T, KS>(L.am, G, it, p.ref_len);
+        out_fold<T, KS, V>(L.am, G, it, p.ref_len);
       } else {
         out_copy<T, KS>(G, it);
       }
@@ -359,30 +400,32 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T>& L,
 
 // The wavefront holding the stored row runs a copy of the pass with that
 // row's register index as a compile-time constant; the others store nothing.
-template <int K, int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
-__device__ __forceinline__ void fwd_pass_out(int out_k, const FwdParams& p, LaneState<R, T>& L,
-                                             const PassGeom& G, const float* prev_row,
-                                             float* s_ref, float* s_hand, float* s_slot) {
+template <int K, int R, int T, int W, int KS, int XL, int KIND, bool CKPT, typename V>
+__device__ __forceinline__ void fwd_pass_out(int out_k, const FwdParams& p,
+                                             LaneState<R, T, V>& L, const PassGeom& G,
+                                             const V* prev_row, V* s_ref, V* s_hand, V* s_slot) {
   if constexpr (K < R) {
     if (out_k == K) {
-      fwd_pass<R, T, W, KS, XL, KIND, CKPT, K>(p, L, G, prev_row, s_ref, s_hand, s_slot);
+      fwd_pass<R, T, W, KS, XL, KIND, CKPT, K, V>(p, L, G, prev_row, s_ref, s_hand, s_slot);
     } else {
-      fwd_pass_out<K + 1, R, T, W, KS, XL, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand,
-                                                   s_slot);
+      fwd_pass_out<K + 1, R, T, W, KS, XL, KIND, CKPT, V>(out_k, p, L, G, prev_row, s_ref,
+                                                          s_hand, s_slot);
     }
   }
 }
 
-// Process every pass of query b with the team of W waves of this workgroup
-// and store its cost and end position.  `row` is this query's row-buffer
-// slot (rows carried from one pass to the next).
-template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
+// Process every pass of query b (with f16x2 values: queries b and b+1, of
+// equal length, or b twice when it is the batch's last) with the team of W
+// waves of this workgroup and store cost and end position.  `row` is the
+// row-buffer slot (rows carried from one pass to the next, as V words).
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, typename V = float>
 __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qoff,
                                           float* __restrict__ row, float* s_mem) {
+  static_assert(!CKPT || Val<V>::N == 1, "checkpoints are binary32 only");
   using S0 = FwdShape<R, T, W, KS, XL>;
-  float* s_ref = s_mem;
-  float* s_hand = s_ref + S0::SR * T;
-  float* s_slot = s_hand + W * S0::SH * T;
+  V* s_ref = reinterpret_cast<V*>(s_mem);
+  V* s_hand = s_ref + S0::SR * T;
+  V* s_slot = s_hand + W * S0::SH * T;
   using S = FwdShape<R, T, W, KS, XL>;
   const int tid = threadIdx.x;
   PassGeom G;
@@ -392,8 +435,10 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   G.n = __builtin_amdgcn_readfirstlane(p.lens[b]);     // uniform: loop bounds below
   G.qoff = qoff;
   G.row = row;
-  G.s_out = s_slot + S0::SLOTS;
+  G.s_out = reinterpret_cast<float*>(s_slot + S0::SLOTS);
   const float* __restrict__ q = p.queries + qoff;
+  // second query of a binary16 pair (the same one at the end of an odd batch)
+  const float* __restrict__ q2 = (Val<V>::N > 1 && b + 1 < p.batch) ? q + G.n : q;
   G.ntiles = (p.ref_len + T - 1) / T;
   const int npass = (G.n + S::ROWS - 1) / S::ROWS;
   const int steps = G.ntiles + S::LL * (kWave * W - 1) + (W - 1) * S::LAG;
@@ -407,20 +452,26 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   for (int pass = 0; pass < npass; ++pass) {
     const int prow0 = pass * S::ROWS;                  // first row of this pass
     G.row0 = prow0 + pos * R;                          // first row of this lane
-    LaneState<R, T> L;
+    LaneState<R, T, V> L;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      L.qv[k] = (G.row0 + k < G.n) ? q[G.row0 + k] : 0.0f;
-      L.dl[k] = inf_f32();
+      const bool in = G.row0 + k < G.n;
+      if constexpr (Val<V>::N == 1) {
+        L.qv[k] = in ? q[G.row0 + k] : 0.0f;
+      } else {
+        L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : 0.0f, in ? q2[G.row0 + k] : 0.0f);
+      }
+      L.dl[k] = Val<V>::inf();
     }
 #pragma unroll
-    for (int t = 0; t < T; ++t) L.bot[t] = inf_f32();
-    L.corner = inf_f32();
+    for (int t = 0; t < T; ++t) L.bot[t] = Val<V>::inf();
+    L.corner = Val<V>::inf();
     L.ck_h = G.my_delay + G.tiles_per_ckpt - 1;        // reaches checkpoint 0 there
     L.ck_k = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) L.ckv[k] = 0.0f;
-    L.am = ValIdx{inf_f32(), 0x7fffffff};
+#pragma unroll
+    for (int h = 0; h < Val<V>::N; ++h) L.am[h] = ValIdx{inf_f32(), 0x7fffffff};
 
     // Row stored by this pass: the pass's last row (to the row buffer), or
     // row N on the final pass (reduced on the fly).
@@ -432,15 +483,15 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     const int out_wave = out_pos / kWave;
     G.out_lane = out_pos - out_wave * kWave;
     G.out_delay = S::LL * out_pos + out_wave * S::LAG;  // out lane's tile = step - out_delay
-    const float* prev_row = pass > 0 ? row : nullptr;
+    const V* prev_row = pass > 0 ? reinterpret_cast<const V*>(row) : nullptr;
 
     // +inf handoff rings and lane slots (a lane before its first tile must
     // see +inf), then the first two intervals of reference and top boundary.
-    for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = inf_f32();
-    for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = inf_f32();
+    for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
+    for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
     __syncthreads();
     {
-      Stager<R, T, W, KS, XL> st0, st1;
+      Stager<R, T, W, KS, XL, V> st0, st1;
       st0.load(p.reference, p.ref_len, prev_row, G.ntiles * T, 0, tid);
       st1.load(p.reference, p.ref_len, prev_row, G.ntiles * T, KS, tid);
       st0.commit(s_ref, s_hand, 0, tid);
@@ -449,16 +500,22 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     __syncthreads();
 
     if (G.wave == out_wave) {
-      fwd_pass_out<0, R, T, W, KS, XL, KIND, CKPT>(out_k, p, L, G, prev_row, s_ref, s_hand, s_slot);
+      fwd_pass_out<0, R, T, W, KS, XL, KIND, CKPT, V>(out_k, p, L, G, prev_row, s_ref, s_hand,
+                                                      s_slot);
       if (last_pass) {
         // every lane of the wave holds the result and stores it (no
         // lane-dependent branch in a loop that holds barriers)
-        const ValIdx x = wave_argmin(L.am);
-        p.cost[b] = x.v;
-        p.end_pos[b] = x.i;
+#pragma unroll
+        for (int h = 0; h < Val<V>::N; ++h) {
+          if (h == 0 || b + h < p.batch) {
+            const ValIdx x = wave_argmin(L.am[h]);
+            p.cost[b + h] = x.v;
+            p.end_pos[b + h] = x.i;
+          }
+        }
       }
     } else {
-      fwd_pass<R, T, W, KS, XL, KIND, CKPT, -1>(p, L, G, prev_row, s_ref, s_hand, s_slot);
+      fwd_pass<R, T, W, KS, XL, KIND, CKPT, -1, V>(p, L, G, prev_row, s_ref, s_hand, s_slot);
     }
   }
 }
@@ -488,6 +545,18 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) 
   const int b = blockIdx.x;
   float* row = p.rowbuf + (int64_t)b * p.row_stride;
   fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem);
+}
+
+// Binary16 form: one workgroup per pair of queries (2i, 2i+1), which must
+// have equal lengths; an odd batch's last query fills both halves.  Each
+// pair owns one row-buffer slot.
+template <int R, int T, int W, int KS, int XL, int KIND>
+__global__ __launch_bounds__(kWave * W) void sdtw_fwd16_kernel(const FwdParams p) {
+  using S = FwdShape<R, T, W, KS, XL>;
+  __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
+  const int b = 2 * (int)blockIdx.x;
+  float* row = p.rowbuf + (int64_t)blockIdx.x * p.row_stride;
+  fwd_query<R, T, W, KS, XL, KIND, false, f16x2>(p, b, query_offset(p, b), row, s_mem);
 }
 
 // Persistent form: a fixed grid pops queries (in the given order, longest

@@ -1,5 +1,6 @@
 // sdtw_variant.hpp -- one compiled forward tile variant: its shape and the
-// kernel entry points for each cost kind and checkpoint mode.
+// kernel entry points for each cost kind and checkpoint mode, and its
+// binary16 form.
 #pragma once
 
 #include "sdtw_fwd.hpp"
@@ -10,6 +11,7 @@ struct Variant {
   int R, T, W, KS, XL;
   const void* plain[2][2];        // [cost kind][checkpoint]
   const void* persistent[2][2];
+  const void* half[2];            // [cost kind]: binary16, two queries per lane row
   int lds_bytes;
 };
 
@@ -29,6 +31,8 @@ Variant make_variant() {
   v.persistent[0][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 0, true>);
   v.persistent[1][0] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, false>);
   v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, true>);
+  v.half[0] = reinterpret_cast<const void*>(&sdtw_fwd16_kernel<R, T, W, KS, XL, 0>);
+  v.half[1] = reinterpret_cast<const void*>(&sdtw_fwd16_kernel<R, T, W, KS, XL, 1>);
   v.lds_bytes = (int)(sizeof(float) * FwdShape<R, T, W, KS, XL>::LDS_FLOATS);
   return v;
 }

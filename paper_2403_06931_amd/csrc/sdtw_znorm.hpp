@@ -43,12 +43,21 @@ __host__ __device__ constexpr int64_t znorm_chunks_of(int64_t n) {
 
 // Element and chunk offsets of every series and the series of every chunk,
 // in one workgroup (the scan of sdtw_offsets_kernel, over two quantities).
+// A thread maps the first kZOwnChunks chunks of its own series; the rest of
+// a longer series (a reference) is mapped by the whole workgroup.
+constexpr int kZOwnChunks = 8;
+constexpr int kZLongMax = 256;                  // long series listed in LDS
+
 __global__ __launch_bounds__(kScanThreads) void sdtw_znorm_index_kernel(
     const int32_t* __restrict__ lens, int32_t batch, int64_t* __restrict__ offsets,
     int64_t* __restrict__ chunk_off, int32_t* __restrict__ chunk_series) {
   __shared__ int64_t s_el[kScanThreads];
   __shared__ int64_t s_ch[kScanThreads];
+  __shared__ int32_t s_long[kZLongMax];
+  __shared__ int64_t s_long_c0[kZLongMax];
+  __shared__ int32_t s_nlong;
   const int tid = threadIdx.x;
+  if (tid == 0) s_nlong = 0;
   const int per = (batch + kScanThreads - 1) / kScanThreads;
   const int lo = min(batch, tid * per), hi = min(batch, lo + per);
   int64_t el = 0, ch = 0;
@@ -72,13 +81,31 @@ __global__ __launch_bounds__(kScanThreads) void sdtw_znorm_index_kernel(
     offsets[i] = re;
     chunk_off[i] = rc;
     const int64_t nc = znorm_chunks_of(lens[i]);
-    for (int64_t k = 0; k < nc; ++k) chunk_series[rc + k] = i;
+    const int64_t own = nc < kZOwnChunks ? nc : kZOwnChunks;
+    for (int64_t k = 0; k < own; ++k) chunk_series[rc + k] = i;
+    if (nc > own) {
+      const int slot = atomicAdd(&s_nlong, 1);
+      if (slot < kZLongMax) {
+        s_long[slot] = i;
+        s_long_c0[slot] = rc;
+      } else {
+        for (int64_t k = own; k < nc; ++k) chunk_series[rc + k] = i;
+      }
+    }
     re += lens[i];
     rc += nc;
   }
   if (tid == kScanThreads - 1) {
     offsets[batch] = s_el[tid];
     chunk_off[batch] = s_ch[tid];
+  }
+  __syncthreads();
+  const int nlong = s_nlong < kZLongMax ? s_nlong : kZLongMax;
+  for (int t = 0; t < nlong; ++t) {
+    const int i = s_long[t];
+    const int64_t c0 = s_long_c0[t];
+    const int64_t nc = znorm_chunks_of(lens[i]);
+    for (int64_t k = kZOwnChunks + tid; k < nc; k += kScanThreads) chunk_series[c0 + k] = i;
   }
 }
 

@@ -211,3 +211,21 @@ def test_align_workspace_smaller_than_backward(L):
     # no per-query reference partials (256 x 50,000 floats)
     assert 0 < a and a + 256 * 50000 * 4 <= b
     assert P.sdtw_align_workspace_bytes(np.array([8193], np.int32), 100, 64) == 0
+
+
+def test_forward_f16_validation(L):
+    import paper_2403_06931_amd as P
+    h = np.array([10, 10, 7], np.int32)
+    assert P.sdtw_forward_f16_workspace_bytes(h, 1000) > 0
+    assert P.sdtw_forward_f16_workspace_bytes(np.array([10, 11], np.int32), 1000) == 0
+    hh = np.ascontiguousarray([10, 11], dtype=np.int32)
+    call = lambda lens, **k: L.lib.sdtw_forward_f16(
+        _vp(k.get("q", FAKE)), _vp(lens.ctypes.data), _vp(FAKE), lens.size, _vp(FAKE), 100,
+        k.get("kind", 0), _vp(k.get("c", FAKE)), _vp(FAKE), -1, _vp(k.get("ws", FAKE)),
+        1 << 40, _vp(0))
+    assert call(hh) == L.SDTW_ERR_UNSUPPORTED            # a pair of unequal lengths
+    h2 = np.ascontiguousarray([10, 10], dtype=np.int32)
+    assert call(h2, q=0) == L.SDTW_ERR_INVALID_ARG
+    assert call(h2, c=0) == L.SDTW_ERR_INVALID_ARG
+    assert call(h2, kind=3) == L.SDTW_ERR_INVALID_ARG
+    assert call(h2, ws=FAKE + 4) == L.SDTW_ERR_INVALID_ARG

@@ -84,3 +84,13 @@ def test_znorm_full_size_batches():
         for k in range(0, len(lens), max(1, len(lens) // 16)):
             v = got[off[k]:off[k + 1]].astype(np.float64)
             assert abs(v.mean()) < 1e-5 and abs(v.std() - 1.0) < 1e-5
+
+
+def test_znorm_many_long_series():
+    """More multi-chunk series than the index kernel lists for its
+    workgroup-wide chunk-map fill (the rest are mapped by their own thread)."""
+    lens = [4096 * 9 + 5] * 300 + [17, 4096 * 8, 4096 * 8 + 1]
+    x = workloads.raw_series(lens, seed=123)
+    want = Z.znorm_f32(x, lens)
+    got = _run(x, lens)
+    _check(got, want, "300 long series")
