@@ -53,8 +53,7 @@ def valu_peak_gcups(ops_per_cell, cus=PEAK_CUS, ghz=PEAK_GHZ, lanes=LANES_PER_CU
 # Sources that define the forward kernel's code (its arithmetic, memory
 # traffic and compile flags); counter summaries are tied to their digest.
 FWD_SOURCES = ("sdtw_common.hpp", "sdtw_argmin.hpp", "sdtw_value.hpp", "sdtw_fwd.hpp",
-               "sdtw_variant.hpp",
-               "sdtw_variant_tu.hip", "build.py")
+               "sdtw_variant.hpp", "sdtw_variant_tu.hip", "build.py")
 
 
 def source_digest():
