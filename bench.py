@@ -18,7 +18,8 @@ Prints ONE JSON line.  Beside the headline value it reports:
                 250..4,000 samples vs 200,000) and the same batch run as a
                 loop of plain launches over 16 length buckets;
   fwd_bwd       forward with checkpoints plus the walk-back gradient
-                (256 x 1,000 vs 50,000);
+                (256 x 1,000 vs 50,000), and the alignment-path output
+                (sdtw_align) on the same forward;
   f16           the same workload in binary16 arithmetic (two queries per
                 packed value), against the packed-FP16 issue rate: gfx950
                 never dual-issues packed (VOP3P) instructions, so its roofline
@@ -234,10 +235,19 @@ def fwd_bwd_leg(P, torch, steps, warmup):
         P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, variant=var,
                        workspace_buf=ws)
     _, p_ms = time_steps(plain, steps, warmup, torch)
+
+    # alignment path output (start position and per-row ranges) from the
+    # same checkpointed forward
+    fwd()
+    wsa = P.workspace(P.sdtw_align_workspace_bytes(w.lens, w.ref_len, K), dev)
+
+    def align():
+        P.sdtw_align(q, w.lens, l, r, 0, cost, end, ckpt, K, workspace_buf=wsa)
+    _, a_ms = time_steps(align, steps, warmup, torch)
     return {"workload": w.name, "cells": w.cells, "ckpt_every": K,
             "gcups": w.cells / (fb_ms * 1e6), "ms_per_step": fb_ms,
             "fwd_ckpt_ms": f_ms, "bwd_ms": b_ms, "plain_fwd_ms": p_ms,
-            "plain_fwd_gcups": w.cells / (p_ms * 1e6),
+            "plain_fwd_gcups": w.cells / (p_ms * 1e6), "align_ms": a_ms,
             "variant": P.sdtw_variant_info(var), "tuned_over": len(rec.get("times_ms", {}))}
 
 
