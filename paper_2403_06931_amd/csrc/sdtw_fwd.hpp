@@ -326,9 +326,7 @@ __device__ __forceinline__ void step_inputs(V (&rv)[T], V (&top)[T], int g, cons
 // Fold the row-N values the out lane wrote during interval `it` (tiles
 // it*KS + s - out_delay, s < KS) into this lane's running (minimum, first
 // minimiser), one per query of the value.  A lane sees the columns in
-// increasing order, so a strict comparison keeps the first minimiser; the
-// index comparison only matters for a row that is +inf throughout (an
-// overflow), whose first column is then reported.
+// increasing order, so a strict comparison keeps the first minimiser.
 template <int T, int KS, typename V>
 __device__ __forceinline__ void out_fold(ValIdx (&am)[Val<V>::N], const PassGeom& G, int it,
                                          int ref_len) {
@@ -341,7 +339,7 @@ __device__ __forceinline__ void out_fold(ValIdx (&am)[Val<V>::N], const PassGeom
 #pragma unroll
     for (int h = 0; h < Val<V>::N; ++h) {
       const float v = Val<V>::half(x, h);
-      if (in && (v < am[h].v || (v == am[h].v && j < am[h].i))) {
+      if (in && v < am[h].v) {
         am[h].v = v;
         am[h].i = j;
       }
@@ -471,7 +469,10 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
 #pragma unroll
     for (int k = 0; k < R; ++k) L.ckv[k] = 0.0f;
 #pragma unroll
-    for (int h = 0; h < Val<V>::N; ++h) L.am[h] = ValIdx{inf_f32(), 0x7fffffff};
+    // (+inf, column 0): a row that is +inf throughout (an overflow) folds
+    // nothing and reports its first column, the smallest index attaining
+    // the minimum; any finite value replaces it
+    for (int h = 0; h < Val<V>::N; ++h) L.am[h] = ValIdx{inf_f32(), 0};
 
     // Row stored by this pass: the pass's last row (to the row buffer), or
     // row N on the final pass (reduced on the fly).

@@ -82,3 +82,18 @@ def test_align_full_size_sampled():
     assert np.array_equal(got[2], start)
     idx = workloads.subset_indices(w, 12, seed=5)
     _check(w, 0, 1024, got, idx)
+
+
+def test_align_degenerate_shapes():
+    """One-sample queries, a one-sample reference, queries longer than the
+    reference."""
+    import paper_2403_06931_amd as P
+    for lens, m, seed in (([1, 1, 2], 50, 1), ([3, 1], 1, 2), ([40, 7], 16, 3)):
+        rng = np.random.default_rng(seed)
+        q = rng.standard_normal(sum(lens)).astype(np.float32)
+        r = rng.standard_normal(m).astype(np.float32)
+        w = workloads.Workload(name="degenerate", queries=q, lens=np.array(lens, np.int32),
+                               reference=r, kinds=(0,), excerpt_start=None, description="")
+        for kind in (0, 1):
+            got = _gpu_align(w, kind, 16)
+            _check(w, kind, 16, got, range(len(lens)))

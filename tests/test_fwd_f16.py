@@ -74,3 +74,17 @@ def test_f16_full_size_sampled():
     sub = w.subset(idx)
     want_c, want_e = oracle.sdtw_f16(sub.queries, sub.lens, sub.reference, 0)
     assert_bit_exact(c[idx], e[idx], want_c, want_e, "f16 512x2000 sample")
+
+
+def test_f16_degenerate_shapes():
+    """One-sample queries and reference, and queries longer than the reference."""
+    for lens, m, seed in (([1, 1], 1, 1), ([1, 1, 5], 50, 2), ([40, 40], 16, 3)):
+        rng = np.random.default_rng(seed)
+        q = rng.standard_normal(sum(lens)).astype(np.float32)
+        r = rng.standard_normal(m).astype(np.float32)
+        w = workloads.Workload(name="degenerate", queries=q, lens=np.array(lens, np.int32),
+                               reference=r, kinds=(0,), excerpt_start=None, description="")
+        for kind in (0, 1):
+            want_c, want_e = oracle.sdtw_f16(q, lens, r, kind)
+            c, e = _gpu_f16(w, kind)
+            assert_bit_exact(c, e, want_c, want_e, f"f16 {lens} vs {m}")
