@@ -53,13 +53,16 @@ constexpr int kBwdMaxSlots = 8;                 // blocks per round per query
 // left).  A lane's 16 cells of a row fill one word from the top: cell c's a
 // is bit 2(15-c)+1 and its u is bit 2(15-c).
 //
-// Shift "x is not a minimum" into the word from below.  DP values are never
-// negative (nor -0), so their bit patterns order like the values: for
-// x >= mn, bits(mn) - bits(x) is zero or has its sign bit set, and
-// v_alignbit_b32 forms (word << 1) | (that sign bit) in one instruction.
+// Shift "x is not a minimum" into the word from below.  For x >= mn the
+// binary32 difference mn - x has its sign bit set exactly when x != mn: it is
+// +0 for equal values (an exact zero difference rounds to +0), negative or -0
+// otherwise (a difference of distinct finite values is never +0), -inf for
+// x = +inf > mn, and a positive NaN for x = mn = +inf.  v_alignbit_b32 then
+// forms (word << 1) | (that sign bit).  The subtraction is an FP32 VALU
+// instruction, which gfx950 dual-issues far more readily than an integer one.
 __device__ __forceinline__ uint32_t push_not_min(uint32_t word, float x, float mn) {
-  const uint32_t d = __builtin_bit_cast(uint32_t, mn) - __builtin_bit_cast(uint32_t, x);
-  return __builtin_amdgcn_alignbit(word, d, 31);
+  const float d = mn - x;
+  return __builtin_amdgcn_alignbit(word, __builtin_bit_cast(uint32_t, d), 31);
 }
 
 struct BwdParams {
