@@ -514,8 +514,13 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
 }
 
 // grad_reference[j] = sum over queries b (increasing) whose path covers
-// column j of ref_part[b][j]; +0 where no path passes.
+// column j of ref_part[b][j]; +0 where no path passes.  The partials of
+// kRefReduceBatch queries are loaded at once (entries outside a query's
+// span were never written and are replaced by +0 before the add; the
+// running sum starts at +0 and is never -0, so adding +0 leaves it
+// unchanged and the result equals the sum over covering queries only).
 constexpr int kRefReduceThreads = 256;
+constexpr int kRefReduceBatch = 8;
 
 __global__ __launch_bounds__(kRefReduceThreads) void sdtw_ref_reduce_kernel(
     const float* __restrict__ ref_part, int64_t part_stride, const int32_t* __restrict__ lo,
@@ -523,7 +528,17 @@ __global__ __launch_bounds__(kRefReduceThreads) void sdtw_ref_reduce_kernel(
   const int j = blockIdx.x * kRefReduceThreads + threadIdx.x;
   if (j >= ref_len) return;
   float acc = 0.0f;
-  for (int b = 0; b < batch; ++b) {
+  int b = 0;
+  for (; b + kRefReduceBatch <= batch; b += kRefReduceBatch) {
+    float v[kRefReduceBatch];
+#pragma unroll
+    for (int u = 0; u < kRefReduceBatch; ++u)
+      v[u] = ref_part[(int64_t)(b + u) * part_stride + j];
+#pragma unroll
+    for (int u = 0; u < kRefReduceBatch; ++u)
+      acc = acc + ((j >= lo[b + u] && j <= (int)hi[b + u]) ? v[u] : 0.0f);
+  }
+  for (; b < batch; ++b) {
     if (j >= lo[b] && j <= (int)hi[b]) acc = acc + ref_part[(int64_t)b * part_stride + j];
   }
   grad_ref[j] = acc;
