@@ -572,7 +572,7 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
            : (qlds ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1, true>)
                    : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1, false>));
     void* args[] = {(void*)&p};
-    if (hipLaunchKernel(grad, dim3(batch), dim3(sdtw::kGradThreads), args,
+    if (hipLaunchKernel(grad, dim3(batch, 2), dim3(sdtw::kGradThreads), args,
                         sdtw::bwd_grad_lds_bytes(nmax), stream) != hipSuccess)
       return SDTW_ERR_HIP;
   }

@@ -412,7 +412,9 @@ __global__ __launch_bounds__(kWave) void sdtw_bwd_round_kernel(const BwdParams p
   }
 }
 
-// Gradients from the recorded path rows.  Grid: batch; kGradThreads threads;
+// Gradients from the recorded path rows.  Grid: (batch, 2): blockIdx.y = 0
+// takes the query sums, 1 the reference partials (independent, so they run
+// side by side); kGradThreads threads;
 // dynamic LDS: the row bounds (2 * max_rows ints) and, with QLDS, the query
 // values (max_rows floats).  Row i's path columns are [row_lo[i], row_hi[i]];
 // both bounds are nondecreasing in i, so the rows of column j are the run
@@ -464,20 +466,34 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
   __syncthreads();
   const float* __restrict__ q = QLDS ? lq : p.queries + qoff;
 
-  for (int i = 1 + tid; i <= n; i += kGradThreads) {
-    const float qi = q[i - 1];
-    const int lo = rlo[i];
-    float acc = 0.0f;
-    int jj = rhi[i];
-    for (; jj - (kGradRowBatch - 1) >= lo; jj -= kGradRowBatch) {
-      float rv[kGradRowBatch];
+  if (blockIdx.y == 0) {
+    for (int i = 1 + tid; i <= n; i += kGradThreads) {
+      const float qi = q[i - 1];
+      const int lo = rlo[i];
+      float acc = 0.0f;
+      int jj = rhi[i];
+      // batches of reference values, the next one loaded while this one is
+      // summed (a row's run can be thousands of columns long)
+      float rv[kGradRowBatch], nx[kGradRowBatch];
+      if (jj - (kGradRowBatch - 1) >= lo) {
 #pragma unroll
-      for (int u = 0; u < kGradRowBatch; ++u) rv[u] = r[jj - u];
+        for (int u = 0; u < kGradRowBatch; ++u) nx[u] = r[jj - u];
+      }
+      for (; jj - (kGradRowBatch - 1) >= lo; jj -= kGradRowBatch) {
 #pragma unroll
-      for (int u = 0; u < kGradRowBatch; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
+        for (int u = 0; u < kGradRowBatch; ++u) rv[u] = nx[u];
+        const int jn = jj - kGradRowBatch;
+        if (jn - (kGradRowBatch - 1) >= lo) {
+#pragma unroll
+          for (int u = 0; u < kGradRowBatch; ++u) nx[u] = r[jn - u];
+        }
+#pragma unroll
+        for (int u = 0; u < kGradRowBatch; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
+      }
+      for (; jj >= lo; --jj) acc = acc + gcost * dcost_dq<KIND>(qi, r[jj]);
+      gq[i - 1] = acc;
     }
-    for (; jj >= lo; --jj) acc = acc + gcost * dcost_dq<KIND>(qi, r[jj]);
-    gq[i - 1] = acc;
+    return;
   }
 
   const int span = jhi - jlo + 1;
