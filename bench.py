@@ -20,6 +20,9 @@ Prints ONE JSON line.  Beside the headline value it reports:
   fwd_bwd       forward with checkpoints plus the walk-back gradient
                 (256 x 1,000 vs 50,000), and the alignment-path output
                 (sdtw_align) on the same forward;
+  long_ref      512 x 2,000 vs a 2,000,000-sample reference, squared and
+                absolute cost (3 VALU instructions per cell: |t| is a source
+                modifier), each against its own roofline;
   f16           the same workload in binary16 arithmetic (two queries per
                 packed value), against the packed-FP16 issue rate: gfx950
                 never dual-issues packed (VOP3P) instructions, so its roofline
@@ -254,6 +257,29 @@ def fwd_bwd_leg(P, torch, steps, warmup):
 HBM_PEAK_GBS = 8000.0
 
 
+def long_ref_leg(P, torch, variant, steps, warmup):
+    """512 x 2,000 vs 2,000,000, both cost kinds, in the headline's tile."""
+    import workloads
+    w = workloads.make_config(2)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
+    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    out = {"workload": w.name, "cells": w.cells, "variant": P.sdtw_variant_info(variant)}
+    for kind, name, ops in ((0, "squared", 4), (1, "absolute", 3)):
+        def step(kind=kind):
+            P.sdtw_forward(q, w.lens, l, r, kind, cost=cost, end_pos=end, variant=variant,
+                           workspace_buf=ws)
+        wall_ms, ev_ms = time_steps(step, steps, warmup, torch)
+        peak = valu_peak_gcups(ops)
+        out[name] = {"ms_per_step": wall_ms, "gcups": w.cells / (wall_ms * 1e6),
+                     "roofline_frac": w.cells / (ev_ms * 1e6) / peak, "peak_gcups": peak}
+    return out
+
+
 def f16_leg(P, torch, steps, warmup):
     """sdtw_forward_f16 on the headline workload; the tile variant is picked
     by timing every compiled variant once (two calls each)."""
@@ -420,6 +446,7 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(P, torch, steps=3, warmup=1)
         out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1)
+        out["long_ref"] = long_ref_leg(P, torch, variant, steps=2, warmup=1)
         out["f16"] = f16_leg(P, torch, steps=5, warmup=1)
         out["znorm"] = znorm_leg(P, torch, steps=20, warmup=3)
     print(json.dumps(out), flush=True)
