@@ -9,7 +9,8 @@ The arithmetic lives in ``sdtw_oracle.c`` (plain C, gcc ``-O2
 -ffp-contract=off``); this module only marshals NumPy arrays through ctypes.
 Every function follows Section 2, Eq. (1) of the paper with the subsequence
 initialisation (row 0 = 0, column 0 = +inf); see the header of
-``sdtw_oracle.c`` for the readings taken where the paper is silent.
+``sdtw_oracle.c`` for the readings taken where the paper is silent.  The
+z-normalisation oracle is ``oracle/znorm.py`` (NumPy, binary64).
 """
 import ctypes
 import os

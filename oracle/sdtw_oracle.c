@@ -34,13 +34,16 @@
  *     diagonal first, then the cell above, then the cell to the left.
  *
  * The FP64 twin widens the FP32 inputs exactly and does all arithmetic in
- * binary64; it is the accuracy reference, not a bit-exact target.
+ * binary64; it is the accuracy reference, not a bit-exact target.  The
+ * binary16 twin (the paper's own precision, Section 5.2) rounds every input
+ * and every operation result to binary16; see oracle_round_f16.
  *
  * Parity pins for every function here live in tests/test_oracle_*.py:
- * brute-force enumeration of all warp paths, a hand-worked DP matrix, the
- * N = 1 closed form, exact-excerpt zeros, path upper bounds, FP32/FP64
- * agreement within the rounding-error bound and finite differences of the
- * FP64 cost for the gradient.
+ * brute-force enumeration of all warp paths (in binary32 and in binary16), a
+ * hand-worked DP matrix, the N = 1 closed form, exact-excerpt zeros, path
+ * upper bounds, FP32/FP64 agreement within the rounding-error bound, finite
+ * differences of the FP64 cost for the gradient, and NumPy's float16
+ * conversion for the binary16 rounding.
  */
 #include <math.h>
 #include <stdint.h>
