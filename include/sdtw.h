@@ -247,11 +247,11 @@ SDTW_API int sdtw_align(const float *queries, const int32_t *h_query_lens,
  *     z_k = (x_k - mean) / S,   mean = (1/n) sum x_k,
  *     S = sqrt((1/n) sum (x_k - mean)^2)   (population standard deviation),
  *
- * with mean, S and the quotient in binary64 and z rounded once to binary32.
- * A constant series (S = 0) maps to zeros (the paper leaves it open).
- * Chunk sums are reduced in a fixed order, so the result does not depend on
- * scheduling; it may differ from another binary64 evaluation order by one
- * binary32 ulp.
+ * with mean and S in binary64, z = (x_k - mean) * (1/S) in binary64 and
+ * rounded once to binary32.  A constant series (S = 0) maps to zeros (the
+ * paper leaves it open).  Chunk sums are reduced in a fixed order, so the
+ * result does not depend on scheduling; it is within one binary32 ulp of the
+ * definition evaluated in binary64 in any other order.
  *
  *   x             packed float32 series [sum h_lens] (packed like queries)
  *   h_lens/lens   host / device int32 [batch] series lengths, each >= 1
