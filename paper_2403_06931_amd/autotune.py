@@ -125,7 +125,11 @@ def tuned_variant(queries, h_lens, query_lens, reference, cost_kind: int = 0,
     cache = _load_cache()
     if mode != "force" and key in cache:
         v = int(cache[key]["best"])
-        if 0 <= v < api.sdtw_variant_count():
+        # a cached index is used only if it still names the same tile (the
+        # library's variant table may have changed since it was tuned)
+        shape = cache[key].get("variants", {}).get(str(v))
+        if 0 <= v < api.sdtw_variant_count() and shape is not None and \
+                tuple(shape) == tuple(api.sdtw_variant_info(v)):
             return v
     rec: dict = {}
     best = tune(queries, h, query_lens, reference, cost_kind, flags, record=rec)

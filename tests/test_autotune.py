@@ -33,6 +33,14 @@ def test_tuner_picks_a_variant_and_caches(tmp_path, monkeypatch):
     assert min(rec["times_ms"].values()) == rec["times_ms"][str(v)]
     # cache hit
     assert P.autotune.tuned_variant(q, w.lens, l, r, 0, 0) == v
+    # an entry whose recorded tile no longer matches the library's table is
+    # not trusted: the batch is tuned again and the entry rewritten
+    rec["variants"][str(v)] = [99, 99, 99, 99, 99]
+    json.dump({key: rec}, open(tmp_path / "tune.json", "w"))
+    v2 = P.autotune.tuned_variant(q, w.lens, l, r, 0, 0)
+    assert 0 <= v2 < P.sdtw_variant_count()
+    rec2 = json.load(open(tmp_path / "tune.json"))[key]
+    assert tuple(rec2["variants"][str(v2)]) == tuple(P.sdtw_variant_info(v2))
     # every variant computes the same bits as the oracle
     want_c, want_e = oracle.sdtw_f32(w.queries, w.lens, w.reference, 0)
     for k in range(P.sdtw_variant_count()):
