@@ -88,3 +88,15 @@ def test_f16_degenerate_shapes():
             want_c, want_e = oracle.sdtw_f16(q, lens, r, kind)
             c, e = _gpu_f16(w, kind)
             assert_bit_exact(c, e, want_c, want_e, f"f16 {lens} vs {m}")
+
+
+def test_f16_large_batch_offset_table():
+    """More queries than the library sums in-kernel (16,384): the offsets come
+    from the one-workgroup scan kernel."""
+    rng = np.random.default_rng(12)
+    pairs = rng.integers(1, 9, 8200)
+    lens = np.repeat(pairs, 2)[:16401]           # 16,401 queries, an odd batch
+    w = workloads.make_random(len(lens), list(lens), 300, seed=13, excerpt_every=0)
+    want_c, want_e = oracle.sdtw_f16(w.queries, w.lens, w.reference, 0)
+    c, e = _gpu_f16(w, 0)
+    assert_bit_exact(c, e, want_c, want_e, "f16 16,401 queries")
