@@ -86,8 +86,9 @@ enum {
 /*
  * Bytes of device workspace sdtw_forward needs for this batch (flags as
  * passed to sdtw_forward).  Returns 0 on invalid arguments.
- * The workspace holds the per-query offset table, the last DP row of each
- * query in flight (from which cost and end_pos are reduced) and, for the
+ * The workspace holds the per-query offset table, one DP row per query in
+ * flight (it carries the last row of a row pass to the next pass for queries
+ * longer than one pass; cost and end_pos are reduced on chip) and, for the
  * persistent form, the work queue.
  */
 SDTW_API size_t sdtw_forward_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
