@@ -88,17 +88,23 @@ def _fp64_check(c32, c64):
 
 def test_paper_shape_sampled():
     """512 x 2,000 against 100,000 (the paper's Section 6 shape): the whole
-    batch on the GPU, eight sampled queries checked against the oracle."""
+    batch on the GPU, in the library's own choice and in the tile the
+    benchmark's tuner picks on this shape ((8, 8, 4, 32) with LDS lane
+    exchange); eight sampled queries checked against the oracle."""
+    import paper_2403_06931_amd as P
     w = workloads.make_config(1)
-    c, e = gpu_forward(w, 0)
     idx = workloads.subset_indices(w, 8)
     sub = w.subset(idx)
     want_c, want_e = oracle.sdtw_f32(sub.queries, sub.lens, sub.reference, 0)
-    assert_bit_exact(c[idx], e[idx], want_c, want_e, "512x2000 vs 100k (sampled)")
     c64, _ = oracle.sdtw_f64(sub.queries, sub.lens, sub.reference, 0)
-    _fp64_check(c[idx], c64)
-    # every result is a real last-row value: end inside the reference, finite cost
-    assert np.all(np.isfinite(c)) and np.all((e >= 0) & (e < w.ref_len))
+    headline = [v for v in range(P.sdtw_variant_count())
+                if P.sdtw_variant_info(v) == (8, 8, 4, 32, 1)]
+    for v in [-1] + headline:
+        c, e = gpu_forward(w, 0, variant=v)
+        assert_bit_exact(c[idx], e[idx], want_c, want_e, f"512x2000 vs 100k, variant {v}")
+        _fp64_check(c[idx], c64)
+        # every result is a real last-row value: end inside the reference, finite cost
+        assert np.all(np.isfinite(c)) and np.all((e >= 0) & (e < w.ref_len))
 
 
 @pytest.mark.parametrize("kind", [0, 1])
