@@ -40,6 +40,8 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.oracle_sdtw_f32.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
                                     ctypes.c_int, _f32p, _i64p, ctypes.c_int]
+    lib.oracle_sdtw_pruned_f32.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
+                                           ctypes.c_float, _f32p, _i64p, ctypes.c_int]
     lib.oracle_sdtw_f64.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
                                     ctypes.c_int, _f64p, _i64p, ctypes.c_int]
     lib.oracle_sdtw_f16.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
@@ -57,7 +59,7 @@ def _load():
                                          ctypes.c_int, _i64p, _i64p]
     lib.oracle_sdtw_path_f32.restype = ctypes.c_int64
     lib.oracle_max_threads.restype = ctypes.c_int
-    for name in ("oracle_sdtw_f32", "oracle_sdtw_f64", "oracle_sdtw_f16", "oracle_sdtw_last_row_f32",
+    for name in ("oracle_sdtw_f32", "oracle_sdtw_pruned_f32", "oracle_sdtw_f64", "oracle_sdtw_f16", "oracle_sdtw_last_row_f32",
                  "oracle_dtw_f32", "oracle_sdtw_grad_f32"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -95,6 +97,23 @@ def sdtw_f32(queries, lens, reference, kind=SQUARED, nthreads=0):
                              int(kind), _p(cost, _f32p), _p(end, _i64p), int(nthreads))
     if rc != 0:
         raise ValueError("oracle_sdtw_f32 rejected its arguments")
+    return cost, end
+
+
+def sdtw_pruned_f32(queries, lens, reference, tau, nthreads=0):
+    """Batched FP32 sDTW with Section 8's early pruning: squared cost, +inf for
+    a pair with |q - r| > tau -> (cost float32 [B], end_pos int64 [B])."""
+    lib = _load()
+    q = _f32(queries).ravel()
+    lens = _lens(q, lens)
+    r = _f32(reference).ravel()
+    cost = np.empty(lens.size, np.float32)
+    end = np.empty(lens.size, np.int64)
+    rc = lib.oracle_sdtw_pruned_f32(_p(q, _f32p), _p(lens, _i32p), lens.size, _p(r, _f32p),
+                                    r.size, float(tau), _p(cost, _f32p), _p(end, _i64p),
+                                    int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_sdtw_pruned_f32 rejected its arguments")
     return cost, end
 
 

@@ -25,6 +25,8 @@
  * Readings where the paper is silent (each one is listed in the design notes):
  *   - d is the squared difference (Section 8 mentions a subtraction followed
  *     by a multiplication) or the absolute difference; kind 0 / kind 1.
+ *     Kind 2 is Section 8's early pruning: the squared difference, but +inf
+ *     when |q - r| > tau (strictly), decided before the multiplication.
  *   - FP32 arithmetic is t = q - r, c = t*t (or |t|), D = m + c, each rounded
  *     to nearest-even, with no fused multiply-add (build with
  *     -ffp-contract=off) and no flush of subnormals.
@@ -53,16 +55,24 @@
 #include <omp.h>
 #endif
 
-enum { ORACLE_SQUARED = 0, ORACLE_ABSOLUTE = 1 };
+enum { ORACLE_SQUARED = 0, ORACLE_ABSOLUTE = 1, ORACLE_PRUNED = 2 };
 
 /* ------------------------------------------------------------------ */
 /* Local cost d(X_i, Y_j) and the exact three-way minimum.             */
 /* ------------------------------------------------------------------ */
 
-static float local_cost_f32(float q, float r, int kind)
+static float local_cost_f32(float q, float r, int kind, float tau)
 {
     float t = q - r;
     if (kind == ORACLE_SQUARED) {
+        float c = t * t;
+        return c;
+    }
+    if (kind == ORACLE_PRUNED) {
+        /* Early pruning (Section 8): decided on the difference, before any
+         * multiplication; a pair farther apart than tau cannot be on the
+         * path and costs +inf. */
+        if (fabsf(t) > tau) return INFINITY;
         float c = t * t;
         return c;
     }
@@ -101,7 +111,7 @@ static double min3_f64(double a, double b, double c)
 /* ------------------------------------------------------------------ */
 
 static void sdtw_one_f32(const float *q, int64_t n, const float *r, int64_t m,
-                         int kind, float *prev, float *cur,
+                         int kind, float tau, float *prev, float *cur,
                          float *cost, int64_t *end_pos)
 {
     for (int64_t j = 0; j <= m; ++j) prev[j] = 0.0f;       /* row 0 */
@@ -109,7 +119,7 @@ static void sdtw_one_f32(const float *q, int64_t n, const float *r, int64_t m,
         cur[0] = INFINITY;                                  /* column 0 */
         float qi = q[i - 1];
         for (int64_t j = 1; j <= m; ++j) {
-            float c = local_cost_f32(qi, r[j - 1], kind);
+            float c = local_cost_f32(qi, r[j - 1], kind, tau);
             float mn = min3_f32(prev[j], cur[j - 1], prev[j - 1]);
             cur[j] = mn + c;
         }
@@ -240,11 +250,10 @@ int oracle_max_threads(void)
  * Batched FP32 sDTW.  queries: packed, query b has lens[b] floats.
  * Returns 0 on success, -1 on a bad argument or allocation failure.
  */
-int oracle_sdtw_f32(const float *queries, const int32_t *lens, int32_t batch,
-                    const float *ref, int64_t ref_len, int kind,
-                    float *cost, int64_t *end_pos, int nthreads)
+static int sdtw_batch_f32(const float *queries, const int32_t *lens, int32_t batch,
+                          const float *ref, int64_t ref_len, int kind, float tau,
+                          float *cost, int64_t *end_pos, int nthreads)
 {
-    if (batch < 1 || ref_len < 1 || (kind != 0 && kind != 1)) return -1;
     for (int32_t b = 0; b < batch; ++b) if (lens[b] < 1) return -1;
     int64_t *off = make_offsets(lens, batch);
     if (!off) return -1;
@@ -260,7 +269,7 @@ int oracle_sdtw_f32(const float *queries, const int32_t *lens, int32_t batch,
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int32_t b = 0; b < batch; ++b)
-                sdtw_one_f32(queries + off[b], lens[b], ref, ref_len, kind,
+                sdtw_one_f32(queries + off[b], lens[b], ref, ref_len, kind, tau,
                              prev, cur, &cost[b], &end_pos[b]);
         }
         free(prev);
@@ -268,6 +277,32 @@ int oracle_sdtw_f32(const float *queries, const int32_t *lens, int32_t batch,
     }
     free(off);
     return failed ? -1 : 0;
+}
+
+/*
+ * Batched FP32 sDTW.  queries: packed, query b has lens[b] floats.
+ * Returns 0 on success, -1 on a bad argument or allocation failure.
+ */
+int oracle_sdtw_f32(const float *queries, const int32_t *lens, int32_t batch,
+                    const float *ref, int64_t ref_len, int kind,
+                    float *cost, int64_t *end_pos, int nthreads)
+{
+    if (batch < 1 || ref_len < 1 || (kind != 0 && kind != 1)) return -1;
+    return sdtw_batch_f32(queries, lens, batch, ref, ref_len, kind, INFINITY,
+                          cost, end_pos, nthreads);
+}
+
+/*
+ * Batched FP32 sDTW with early pruning (Section 8): the squared cost, except
+ * that a pair with |q - r| > tau costs +inf.  tau must not be NaN.
+ */
+int oracle_sdtw_pruned_f32(const float *queries, const int32_t *lens, int32_t batch,
+                           const float *ref, int64_t ref_len, float tau,
+                           float *cost, int64_t *end_pos, int nthreads)
+{
+    if (batch < 1 || ref_len < 1 || isnan(tau)) return -1;
+    return sdtw_batch_f32(queries, lens, batch, ref, ref_len, ORACLE_PRUNED, tau,
+                          cost, end_pos, nthreads);
 }
 
 /* Batched FP64 twin of oracle_sdtw_f32 (inputs widened exactly). */
@@ -349,7 +384,7 @@ int oracle_sdtw_last_row_f32(const float *q, int32_t n, const float *ref,
     for (int64_t i = 1; i <= n; ++i) {
         cur[0] = INFINITY;
         for (int64_t j = 1; j <= ref_len; ++j) {
-            float c = local_cost_f32(q[i - 1], ref[j - 1], kind);
+            float c = local_cost_f32(q[i - 1], ref[j - 1], kind, INFINITY);
             cur[j] = min3_f32(prev[j], cur[j - 1], prev[j - 1]) + c;
         }
         float *t = prev; prev = cur; cur = t;
@@ -377,7 +412,7 @@ int oracle_dtw_f32(const float *q, int32_t n, const float *ref,
     for (int64_t i = 1; i <= n; ++i) {
         cur[0] = INFINITY;
         for (int64_t j = 1; j <= ref_len; ++j) {
-            float c = local_cost_f32(q[i - 1], ref[j - 1], kind);
+            float c = local_cost_f32(q[i - 1], ref[j - 1], kind, INFINITY);
             cur[j] = min3_f32(prev[j], cur[j - 1], prev[j - 1]) + c;
         }
         float *t = prev; prev = cur; cur = t;
@@ -424,7 +459,7 @@ static void sdtw_full_and_walk(const float *q, int64_t n, const float *r,
         const float *up = D + (i - 1) * s;
         row[0] = INFINITY;
         for (int64_t j = 1; j <= m; ++j) {
-            float c = local_cost_f32(q[i - 1], r[j - 1], kind);
+            float c = local_cost_f32(q[i - 1], r[j - 1], kind, INFINITY);
             row[j] = min3_f32(up[j], row[j - 1], up[j - 1]) + c;
         }
     }
