@@ -314,6 +314,59 @@ def f16_leg(P, torch, steps, warmup):
                                        "dual-issued) x 2.4 GHz / 2.5 VALU ops per cell"}}
 
 
+def pruned_leg(P, torch, exact_cost, exact_end, steps, warmup):
+    """sdtw_forward_pruned (Section 8's early pruning) on the headline
+    workload: speed at tau = 2 in the fastest variant (each timed once), and,
+    for several tau, how many queries keep their exact cost and end position
+    (exact_cost / exact_end: the squared-cost forward's outputs)."""
+    import numpy as np
+
+    import workloads
+    w = workloads.make_config(1)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
+    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    tau0 = 2.0
+    times = {}
+    for v in range(P.sdtw_variant_count()):
+        def run(v=v):
+            P.sdtw_forward_pruned(q, w.lens, l, r, tau0, cost=cost, end_pos=end, variant=v,
+                                  workspace_buf=ws)
+        times[v] = time_steps(run, 1, 1, torch)[1]
+    best = min(times, key=times.get)
+
+    def step():
+        P.sdtw_forward_pruned(q, w.lens, l, r, tau0, cost=cost, end_pos=end, variant=best,
+                              workspace_buf=ws)
+    wall_ms, ev_ms = time_steps(step, steps, warmup, torch)
+    peak = valu_peak_gcups(7)
+    accuracy = {}
+    for tau in (0.5, 1.0, 2.0, 3.0, 4.0):
+        P.sdtw_forward_pruned(q, w.lens, l, r, tau, cost=cost, end_pos=end, variant=best,
+                              workspace_buf=ws)
+        c = cost.cpu().numpy()
+        e = end.cpu().numpy()
+        same = (c.view(np.uint32) == exact_cost.view(np.uint32)) & (e == exact_end)
+        fin = np.isfinite(c)
+        pos = fin & (exact_cost > 0)
+        accuracy[str(tau)] = {"exact_queries": int(same.sum()), "pruned_to_inf": int((~fin).sum()),
+                              "median_cost_ratio": float(np.median(c[pos] / exact_cost[pos]))
+                              if pos.any() else None}
+    return {"workload": w.name, "tau": tau0, "cells": w.cells, "ms_per_step": wall_ms,
+            "gcups": w.cells / (wall_ms * 1e6), "kernel_ms": ev_ms,
+            "variant": P.sdtw_variant_info(best),
+            "speed_vs_exact_kernel": None,
+            "roofline": {"bound": "alu", "achieved": w.cells / (ev_ms * 1e6), "peak": peak,
+                         "unit": "GCUPS", "frac": w.cells / (ev_ms * 1e6) / peak,
+                         "peak_basis": "256 CU x 128 lanes/clk (VALU dual issue) x 2.4 GHz / "
+                                       "7 VALU ops per cell"},
+            "accuracy_of_512_queries": accuracy}
+
+
 def znorm_leg(P, torch, steps, warmup):
     """sdtw_znorm on raw (unnormalised) series of the evaluation's shapes."""
     import numpy as np
@@ -448,6 +501,8 @@ def main():
         out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1)
         out["long_ref"] = long_ref_leg(P, torch, variant, steps=2, warmup=1)
         out["f16"] = f16_leg(P, torch, steps=5, warmup=1)
+        out["pruned"] = pruned_leg(P, torch, gc, ge, steps=5, warmup=1)
+        out["pruned"]["speed_vs_exact_kernel"] = ev_ms / out["pruned"]["kernel_ms"]
         out["znorm"] = znorm_leg(P, torch, steps=20, warmup=3)
     print(json.dumps(out), flush=True)
 

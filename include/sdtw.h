@@ -138,6 +138,28 @@ SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
                  void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Forward pass with early pruning, the cost rule Section 8 proposes: after
+ * the subtraction t = q_i - r_j, a pair with |t| > prune_tau is taken to be
+ * unable to lie on the warp path and costs +inf (no multiplication);
+ * otherwise the cost is t*t, as for SDTW_COST_SQUARED.  Everything else is
+ * sdtw_forward's: the same DP, outputs, variants and workspace
+ * (sdtw_forward_workspace_bytes with the same flags).  The result is an
+ * approximation of the squared-cost sDTW: cost[b] >= the exact cost, equal
+ * whenever some optimal path has every |t| <= prune_tau (always for
+ * prune_tau = +inf); a query with no such path gets +inf and end_pos 0.
+ *
+ *   prune_tau  any float32 but NaN (NaN: SDTW_ERR_INVALID_ARG); a negative
+ *              value prunes every pair
+ *   flags      0 or SDTW_F_PERSISTENT (checkpoints: SDTW_ERR_INVALID_ARG)
+ *   other arguments as for sdtw_forward
+ */
+SDTW_API int sdtw_forward_pruned(const float *queries, const int32_t *h_query_lens,
+                        const int32_t *query_lens, int32_t batch,
+                        const float *reference, int64_t ref_len, float prune_tau,
+                        float *cost, int64_t *end_pos, int32_t variant, int32_t flags,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Bytes of device workspace sdtw_backward needs: per-query reference
  * partials (batch x ref_len floats), per-row path bounds, and 2-bit direction
  * codes for the blocks recomputed at once (up to 8 blocks of ckpt_every

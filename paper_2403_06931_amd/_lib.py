@@ -55,6 +55,10 @@ def _load():
                                  ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
     lib.sdtw_forward.restype = ctypes.c_int
+    lib.sdtw_forward_pruned.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
+                                        ctypes.c_float, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                        _vp, ctypes.c_size_t, _vp]
+    lib.sdtw_forward_pruned.restype = ctypes.c_int
     lib.sdtw_backward_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64,
                                                   ctypes.c_int32]
     lib.sdtw_backward_workspace_bytes.restype = ctypes.c_size_t

@@ -126,6 +126,39 @@ def sdtw_forward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
     return cost, end_pos
 
 
+def sdtw_forward_pruned(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
+                        reference: torch.Tensor, prune_tau: float, *,
+                        cost: Optional[torch.Tensor] = None,
+                        end_pos: Optional[torch.Tensor] = None,
+                        variant: int = -1, flags: int = 0,
+                        workspace_buf: Optional[torch.Tensor] = None,
+                        stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Squared-cost forward with early pruning: a pair with |q - r| > prune_tau
+    costs +inf.  Same outputs and workspace as sdtw_forward (flags 0 or
+    SDTW_F_PERSISTENT)."""
+    h = _host_lens(h_query_lens)
+    _require_cuda("queries", queries, torch.float32)
+    _require_cuda("query_lens", query_lens, torch.int32)
+    _require_cuda("reference", reference, torch.float32)
+    dev = queries.device
+    b = h.size
+    if cost is None:
+        cost = torch.empty(b, dtype=torch.float32, device=dev)
+    if end_pos is None:
+        end_pos = torch.empty(b, dtype=torch.int64, device=dev)
+    need = sdtw_forward_workspace_bytes(h, reference.numel(), flags)
+    if need == 0:
+        raise SdtwError(_lib.SDTW_ERR_INVALID_ARG, "sdtw_forward_workspace_bytes")
+    if workspace_buf is None:
+        workspace_buf = workspace(need, dev)
+    st = _lib.lib.sdtw_forward_pruned(
+        _dp(queries), _hp(h), _dp(query_lens), b, _dp(reference), reference.numel(),
+        float(prune_tau), _dp(cost), _dp(end_pos), int(variant), int(flags),
+        _dp(workspace_buf), workspace_buf.numel(), _stream(stream))
+    check(st, "sdtw_forward_pruned")
+    return cost, end_pos
+
+
 def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
                   reference: torch.Tensor, cost_kind: int, grad_cost: torch.Tensor,
                   cost: torch.Tensor, end_pos: torch.Tensor, ckpt: Optional[torch.Tensor],

@@ -388,8 +388,14 @@ size_t sdtw_checkpoint_floats(const int32_t* h_query_lens, int32_t batch, int64_
   return nck > 0 ? (size_t)(total * nck) : 0;
 }
 
-int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
-                 int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
+}  // extern "C"
+
+namespace {
+
+// sdtw_forward and sdtw_forward_pruned: kind is kSquared, kAbsolute or
+// kPruned (threshold tau; no checkpoints).
+int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
+                 int32_t batch, const float* reference, int64_t ref_len, int cost_kind, float tau,
                  float* cost, int64_t* end_pos, float* ckpt, int32_t ckpt_every, int32_t variant_id,
                  int32_t flags, void* workspace, size_t workspace_bytes, void* stream_ptr) {
   int64_t total = 0;
@@ -397,8 +403,6 @@ int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_
   if (!queries || !query_lens || !reference || !cost || !end_pos || !workspace)
     return SDTW_ERR_INVALID_ARG;
   if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
-    return SDTW_ERR_INVALID_ARG;
-  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
     return SDTW_ERR_INVALID_ARG;
   if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return SDTW_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
@@ -437,7 +441,9 @@ int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_
   p.ref_len = (int32_t)ref_len;
   p.ckpt_every = want_ckpt ? ckpt_every : 0;
   p.n_ckpt = (int32_t)nck;
+  p.prune_tau = tau;
   const int ck = p.ckpt != nullptr ? 1 : 0;
+  const bool pruned = cost_kind == sdtw::kPruned;
 
   if (batch > kInKernelOffsetBatch) {
     int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
@@ -460,10 +466,39 @@ int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_
     if (rc != SDTW_OK) return rc;
     const int grid = (int)std::min<int64_t>(L.slots, persistent_grid_for(v, device_cus()));
     void* args[] = {(void*)&p};
-    return launch(v.persistent[cost_kind][ck], dim3(grid), dim3(64 * v.W), args, stream);
+    return launch(pruned ? v.pruned[1] : v.persistent[cost_kind][ck], dim3(grid),
+                  dim3(64 * v.W), args, stream);
   }
   void* args[] = {(void*)&p};
-  return launch(v.plain[cost_kind][ck], dim3(batch), dim3(64 * v.W), args, stream);
+  return launch(pruned ? v.pruned[0] : v.plain[cost_kind][ck], dim3(batch), dim3(64 * v.W),
+                args, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
+                 int32_t batch, const float* reference, int64_t ref_len, int32_t cost_kind,
+                 float* cost, int64_t* end_pos, float* ckpt, int32_t ckpt_every, int32_t variant_id,
+                 int32_t flags, void* workspace, size_t workspace_bytes, void* stream_ptr) {
+  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
+    return SDTW_ERR_INVALID_ARG;
+  return forward_impl(queries, h_query_lens, query_lens, batch, reference, ref_len, cost_kind,
+                      0.0f, cost, end_pos, ckpt, ckpt_every, variant_id, flags, workspace,
+                      workspace_bytes, stream_ptr);
+}
+
+int sdtw_forward_pruned(const float* queries, const int32_t* h_query_lens,
+                        const int32_t* query_lens, int32_t batch, const float* reference,
+                        int64_t ref_len, float prune_tau, float* cost, int64_t* end_pos,
+                        int32_t variant_id, int32_t flags, void* workspace,
+                        size_t workspace_bytes, void* stream_ptr) {
+  if (prune_tau != prune_tau) return SDTW_ERR_INVALID_ARG;          // NaN
+  if (flags & ~SDTW_F_PERSISTENT) return SDTW_ERR_INVALID_ARG;      // no checkpoints
+  return forward_impl(queries, h_query_lens, query_lens, batch, reference, ref_len,
+                      sdtw::kPruned, prune_tau, cost, end_pos, nullptr, 0, variant_id, flags,
+                      workspace, workspace_bytes, stream_ptr);
 }
 
 size_t sdtw_forward_f16_workspace_bytes(const int32_t* h_query_lens, int32_t batch,

@@ -62,6 +62,7 @@ struct FwdParams {
   int32_t ref_len;
   int32_t ckpt_every;       // multiple of T when ckpt != nullptr
   int32_t n_ckpt;           // ceil(ref_len / ckpt_every) - 1
+  float prune_tau;          // pruning threshold of the kPruned cost kind
 };
 
 constexpr int kStepsPerBarrier = 8;
@@ -155,6 +156,7 @@ struct LaneState {
   int ck_k;        // index of that checkpoint (0-based)
   float ckv[R];    // the lane's rows at the last checkpoint column reached
   ValIdx am[Val<V>::N];   // running (minimum, first minimiser) of row N, per query
+  float tau;       // pruning threshold (kPruned), held in a vector register
 };
 
 // Uniform (per wavefront) geometry of one pass.
@@ -224,7 +226,7 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
         const V u = k == 0 ? up[t] : D[k - 1][t];
         const V lf = t == 0 ? L.dl[k] : D[k][t - 1];
         const V dg = t == 0 ? (k == 0 ? upleft : L.dl[k - 1]) : (k == 0 ? up[t - 1] : D[k - 1][t - 1]);
-        const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t]);
+        const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t], L.tau);
         D[k][t] = Val<V>::add(Val<V>::min3(u, lf, dg), c);
       }
     }
@@ -249,7 +251,7 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
     V cur[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t]);
+      const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t], L.tau);
       const V mn = Val<V>::min3(up[t], left, diag);
       cur[t] = Val<V>::add(mn, c);
       diag = up[t];
@@ -473,6 +475,8 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     // nothing and reports its first column, the smallest index attaining
     // the minimum; any finite value replaces it
     for (int h = 0; h < Val<V>::N; ++h) L.am[h] = ValIdx{inf_f32(), 0};
+    L.tau = 0.0f;
+    if constexpr (KIND == kPruned) L.tau = vgpr_copy(p.prune_tau);
 
     // Row stored by this pass: the pass's last row (to the row buffer), or
     // row N on the final pass (reduced on the fly).

@@ -32,7 +32,7 @@ struct Val<float> {
   __device__ static float query(float a, float) { return a; }
   __device__ static float ref(float r) { return r; }
   template <int KIND>
-  __device__ static float cost(float q, float r) { return local_cost<KIND>(q, r); }
+  __device__ static float cost(float q, float r, float tau) { return local_cost<KIND>(q, r, tau); }
   __device__ static float min3(float a, float b, float c) { return sdtw::min3(a, b, c); }
   __device__ static float add(float a, float b) { return a + b; }
   __device__ static float shr1(float lane0, float v) { return wave_shr1(lane0, v); }
@@ -55,7 +55,8 @@ struct Val<f16x2> {
     return f16x2{h, h};
   }
   template <int KIND>
-  __device__ static f16x2 cost(f16x2 q, f16x2 r) {
+  __device__ static f16x2 cost(f16x2 q, f16x2 r, float) {
+    static_assert(KIND != kPruned, "pruning is a binary32 cost kind");
     const f16x2 t = q - r;                     // v_pk_add_f16 with a negated operand
     if constexpr (KIND == kSquared) {
       return t * t;                            // v_pk_mul_f16

@@ -1,6 +1,6 @@
 // sdtw_variant.hpp -- one compiled forward tile variant: its shape and the
-// kernel entry points for each cost kind and checkpoint mode, and its
-// binary16 form.
+// kernel entry points for each cost kind and checkpoint mode, its pruned
+// form and its binary16 form.
 #pragma once
 
 #include "sdtw_fwd.hpp"
@@ -12,6 +12,7 @@ struct Variant {
   const void* plain[2][2];        // [cost kind][checkpoint]
   const void* persistent[2][2];
   const void* half[2];            // [cost kind]: binary16, two queries per lane row
+  const void* pruned[2];          // squared cost with early pruning: [plain, persistent]
   int lds_bytes;
 };
 
@@ -31,6 +32,8 @@ Variant make_variant() {
   v.persistent[0][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 0, true>);
   v.persistent[1][0] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, false>);
   v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, true>);
+  v.pruned[0] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, XL, kPruned, false>);
+  v.pruned[1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, kPruned, false>);
   v.half[0] = reinterpret_cast<const void*>(&sdtw_fwd16_kernel<R, T, W, KS, XL, 0>);
   v.half[1] = reinterpret_cast<const void*>(&sdtw_fwd16_kernel<R, T, W, KS, XL, 1>);
   v.lds_bytes = (int)(sizeof(float) * FwdShape<R, T, W, KS, XL>::LDS_FLOATS);

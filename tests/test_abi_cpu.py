@@ -229,3 +229,20 @@ def test_forward_f16_validation(L):
     assert call(h2, c=0) == L.SDTW_ERR_INVALID_ARG
     assert call(h2, kind=3) == L.SDTW_ERR_INVALID_ARG
     assert call(h2, ws=FAKE + 4) == L.SDTW_ERR_INVALID_ARG
+
+
+def test_forward_pruned_validation(L):
+    FAKE = 1 << 20
+    h = np.ascontiguousarray([10, 12], dtype=np.int32)
+    call = lambda **k: L.lib.sdtw_forward_pruned(
+        _vp(k.get("q", FAKE)), _vp(h.ctypes.data), _vp(FAKE), h.size, _vp(FAKE), 100,
+        k.get("tau", 1.0), _vp(k.get("c", FAKE)), _vp(FAKE), k.get("v", -1), k.get("flags", 0),
+        _vp(k.get("ws", FAKE)), k.get("wsb", 1 << 40), _vp(0))
+    assert call(tau=float("nan")) == L.SDTW_ERR_INVALID_ARG
+    assert call(flags=L.SDTW_F_CHECKPOINT) == L.SDTW_ERR_INVALID_ARG
+    assert call(flags=8) == L.SDTW_ERR_INVALID_ARG
+    assert call(q=0) == L.SDTW_ERR_INVALID_ARG
+    assert call(c=0) == L.SDTW_ERR_INVALID_ARG
+    assert call(ws=FAKE + 4) == L.SDTW_ERR_INVALID_ARG
+    assert call(wsb=16) == L.SDTW_ERR_WORKSPACE
+    assert call(v=10_000) == L.SDTW_ERR_UNSUPPORTED
