@@ -42,6 +42,9 @@ def _load():
                                     ctypes.c_int, _f32p, _i64p, ctypes.c_int]
     lib.oracle_sdtw_pruned_f32.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
                                            ctypes.c_float, _f32p, _i64p, ctypes.c_int]
+    lib.oracle_sdtw_codes.argtypes = [ctypes.POINTER(ctypes.c_uint8), _i32p, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64, _i64p,
+                                      _i64p, ctypes.c_int]
     lib.oracle_sdtw_f64.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
                                     ctypes.c_int, _f64p, _i64p, ctypes.c_int]
     lib.oracle_sdtw_f16.argtypes = [_f32p, _i32p, ctypes.c_int32, _f32p, ctypes.c_int64,
@@ -59,7 +62,7 @@ def _load():
                                          ctypes.c_int, _i64p, _i64p]
     lib.oracle_sdtw_path_f32.restype = ctypes.c_int64
     lib.oracle_max_threads.restype = ctypes.c_int
-    for name in ("oracle_sdtw_f32", "oracle_sdtw_pruned_f32", "oracle_sdtw_f64", "oracle_sdtw_f16", "oracle_sdtw_last_row_f32",
+    for name in ("oracle_sdtw_f32", "oracle_sdtw_pruned_f32", "oracle_sdtw_codes", "oracle_sdtw_f64", "oracle_sdtw_f16", "oracle_sdtw_last_row_f32",
                  "oracle_dtw_f32", "oracle_sdtw_grad_f32"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -114,6 +117,23 @@ def sdtw_pruned_f32(queries, lens, reference, tau, nthreads=0):
                                     int(nthreads))
     if rc != 0:
         raise ValueError("oracle_sdtw_pruned_f32 rejected its arguments")
+    return cost, end
+
+
+def sdtw_codes(qcodes, lens, rcodes, nthreads=0):
+    """Batched sDTW on uint8 codes, local cost (a - b)^2, exact integers ->
+    (cost int64 [B], end_pos int64 [B])."""
+    lib = _load()
+    q = np.ascontiguousarray(qcodes, dtype=np.uint8).ravel()
+    lens = _lens(q, lens)
+    r = np.ascontiguousarray(rcodes, dtype=np.uint8).ravel()
+    cost = np.empty(lens.size, np.int64)
+    end = np.empty(lens.size, np.int64)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    rc = lib.oracle_sdtw_codes(_p(q, u8p), _p(lens, _i32p), lens.size, _p(r, u8p), r.size,
+                               _p(cost, _i64p), _p(end, _i64p), int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle_sdtw_codes rejected its arguments")
     return cost, end
 
 

@@ -604,3 +604,63 @@ int64_t oracle_sdtw_path_f32(const float *q, int32_t n, const float *ref,
     free(D);
     return plen;
 }
+
+/* ------------------------------------------------------------------ */
+/* sDTW on uint8 codes (Section 8's proposed quantisation): the same    */
+/* recurrence, with the local cost (a - b)^2 of two codes, in exact     */
+/* integer arithmetic.                                                  */
+/* ------------------------------------------------------------------ */
+
+static void sdtw_one_codes(const uint8_t *q, int64_t n, const uint8_t *r, int64_t m,
+                           int64_t *prev, int64_t *cur, int64_t *cost, int64_t *end_pos)
+{
+    const int64_t inf = INT64_MAX;                  /* column 0; never added to */
+    for (int64_t j = 0; j <= m; ++j) prev[j] = 0;   /* row 0 */
+    for (int64_t i = 1; i <= n; ++i) {
+        cur[0] = inf;
+        for (int64_t j = 1; j <= m; ++j) {
+            int64_t t = (int64_t)q[i - 1] - (int64_t)r[j - 1];
+            int64_t mn = prev[j];
+            if (cur[j - 1] < mn) mn = cur[j - 1];
+            if (prev[j - 1] < mn) mn = prev[j - 1];
+            cur[j] = mn + t * t;
+        }
+        int64_t *tmp = prev; prev = cur; cur = tmp;
+    }
+    int64_t best = prev[1], arg = 1;
+    for (int64_t j = 2; j <= m; ++j)
+        if (prev[j] < best) { best = prev[j]; arg = j; }
+    *cost = best;
+    *end_pos = arg - 1;
+}
+
+/* Batched sDTW on codes; queries packed like oracle_sdtw_f32's. */
+int oracle_sdtw_codes(const uint8_t *queries, const int32_t *lens, int32_t batch,
+                      const uint8_t *ref, int64_t ref_len, int64_t *cost, int64_t *end_pos,
+                      int nthreads)
+{
+    if (batch < 1 || ref_len < 1) return -1;
+    for (int32_t b = 0; b < batch; ++b) if (lens[b] < 1) return -1;
+    int64_t *off = make_offsets(lens, batch);
+    if (!off) return -1;
+    int failed = 0;
+    set_threads(nthreads);
+#pragma omp parallel
+    {
+        int64_t *prev = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ref_len + 1));
+        int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ref_len + 1));
+        if (!prev || !cur) {
+#pragma omp atomic write
+            failed = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int32_t b = 0; b < batch; ++b)
+                sdtw_one_codes(queries + off[b], lens[b], ref, ref_len, prev, cur,
+                               &cost[b], &end_pos[b]);
+        }
+        free(prev);
+        free(cur);
+    }
+    free(off);
+    return failed ? -1 : 0;
+}
