@@ -27,6 +27,13 @@ Prints ONE JSON line.  Beside the headline value it reports:
                 packed value), against the packed-FP16 issue rate: gfx950
                 never dual-issues packed (VOP3P) instructions, so its roofline
                 is 256 CUs x 64 lanes x 2.4 GHz / 2.5 instructions per cell;
+  pruned        the same workload with Section 8's early pruning (+inf cost
+                for |q - r| > tau), 7 VALU instructions per cell, and how many
+                queries keep their exact result at several tau;
+  u8            the same workload on uint8 codes (Section 8's codebook
+                quantisation): codebook, codes and an exact integer DP of 3
+                VALU instructions per cell, with the error of the scaled cost
+                against the exact one;
   znorm         the batch z-normaliser that prepares the inputs, against
                 the 8 TB/s HBM roofline (8 algorithmic bytes per sample:
                 one read, one write).
@@ -367,6 +374,58 @@ def pruned_leg(P, torch, exact_cost, exact_end, steps, warmup):
             "accuracy_of_512_queries": accuracy}
 
 
+def u8_leg(P, torch, exact_cost, exact_end, steps, warmup):
+    """sdtw_forward_u8 (Section 8's uint8 codebook quantisation) on the
+    headline workload: one call builds the codebook, codes queries and
+    reference and runs the integer DP; the fastest variant (each timed once)
+    is timed, and its results are compared with the exact FP32 ones
+    (exact_cost / exact_end)."""
+    import numpy as np
+
+    import workloads
+    w = workloads.make_config(1)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(w.queries).to(dev)
+    l = torch.from_numpy(w.lens).to(dev)
+    r = torch.from_numpy(w.reference).to(dev)
+    ws = P.workspace(P.sdtw_forward_u8_workspace_bytes(w.lens, w.ref_len), dev)
+    cost = torch.empty(w.batch, dtype=torch.int32, device=dev)
+    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
+    book = torch.empty(2, dtype=torch.float32, device=dev)
+    times = {}
+    for v in range(P.sdtw_variant_count()):
+        def run(v=v):
+            P.sdtw_forward_u8(q, w.lens, l, r, cost_codes=cost, end_pos=end, codebook=book,
+                              variant=v, workspace_buf=ws)
+        times[v] = time_steps(run, 1, 1, torch)[1]
+    best = min(times, key=times.get)
+
+    def step():
+        P.sdtw_forward_u8(q, w.lens, l, r, cost_codes=cost, end_pos=end, codebook=book,
+                          variant=best, workspace_buf=ws)
+    wall_ms, ev_ms = time_steps(step, steps, warmup, torch)
+    lo, hi = (float(x) for x in book.cpu().numpy())
+    s2 = ((hi - lo) / 255.0) ** 2
+    c = cost.cpu().numpy().view(np.uint32).astype(np.float64) * s2
+    e = end.cpu().numpy()
+    pos = exact_cost > 0
+    rel = np.abs(c[pos] - exact_cost[pos]) / exact_cost[pos]
+    peak = valu_peak_gcups(3)
+    return {"workload": w.name, "cells": w.cells, "ms_per_step": wall_ms,
+            "gcups": w.cells / (wall_ms * 1e6), "call_ms": ev_ms,
+            "variant": P.sdtw_variant_info(best), "codebook": [lo, hi],
+            "speed_vs_exact_kernel": None,
+            "roofline": {"bound": "alu", "achieved": w.cells / (ev_ms * 1e6), "peak": peak,
+                         "unit": "GCUPS", "frac": w.cells / (ev_ms * 1e6) / peak,
+                         "peak_basis": "256 CU x 128 lanes/clk (VALU dual issue) x 2.4 GHz / "
+                                       "3 VALU ops per cell (sub, mad_i24, min3); achieved "
+                                       "over the whole call (codebook, codes, DP)"},
+            "accuracy_of_512_queries": {
+                "same_end_pos": int((e == exact_end).sum()),
+                "median_rel_cost_error": float(np.median(rel)) if rel.size else None,
+                "max_rel_cost_error": float(rel.max()) if rel.size else None}}
+
+
 def znorm_leg(P, torch, steps, warmup):
     """sdtw_znorm on raw (unnormalised) series of the evaluation's shapes."""
     import numpy as np
@@ -503,6 +562,8 @@ def main():
         out["f16"] = f16_leg(P, torch, steps=5, warmup=1)
         out["pruned"] = pruned_leg(P, torch, gc, ge, steps=5, warmup=1)
         out["pruned"]["speed_vs_exact_kernel"] = ev_ms / out["pruned"]["kernel_ms"]
+        out["u8"] = u8_leg(P, torch, gc, ge, steps=5, warmup=1)
+        out["u8"]["speed_vs_exact_kernel"] = ev_ms / out["u8"]["call_ms"]
         out["znorm"] = znorm_leg(P, torch, steps=20, warmup=3)
     print(json.dumps(out), flush=True)
 

@@ -153,6 +153,44 @@ SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
  *   flags      0 or SDTW_F_PERSISTENT (checkpoints: SDTW_ERR_INVALID_ARG)
  *   other arguments as for sdtw_forward
  */
+/*
+ * Bytes of device workspace sdtw_forward_u8 needs: sdtw_forward's (no flags),
+ * one byte per query and reference element for the codes, and the codebook.
+ * Returns 0 on invalid arguments or when a query is longer than 32,768 rows.
+ */
+SDTW_API size_t sdtw_forward_u8_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
+                                       int64_t ref_len);
+
+/*
+ * Forward pass on uint8 codes, the quantisation Section 8 proposes: a
+ * codebook built from the reference's values whose bulk is divided evenly
+ * over 256 codes, outliers clamped to the end codes.  For z-normalised
+ * inputs the bulk is taken as the values within 4 standard deviations of the
+ * mean:
+ *   lo = max(min(reference), -4),  hi = min(max(reference), 4),
+ *   code(x) = clamp(rint((x - lo) * 255 / (hi - lo)), 0, 255)
+ * in binary64, round half to even (every code 0 when hi <= lo).  The DP of
+ * sdtw_forward then runs exactly in 32-bit integers on the codes with the
+ * local cost (a - b)^2, so cost_codes * step^2, step = (hi - lo) / 255,
+ * approximates the squared-cost sDTW of the original values.
+ *
+ *   queries, h_query_lens, query_lens, batch, reference, ref_len, variant,
+ *                stream: as for sdtw_forward; queries at most 32,768 rows
+ *                (SDTW_ERR_UNSUPPORTED otherwise, which keeps every DP value
+ *                below 2^31)
+ *   cost_codes   device uint32 [batch]: minimum of the last row, in units of
+ *                step^2 (output)
+ *   end_pos      device int64 [batch], 0-based, first minimiser (output)
+ *   codebook     device float32 [2]: lo, hi (output)
+ *   workspace    device, >= sdtw_forward_u8_workspace_bytes(...) bytes,
+ *                256-byte aligned
+ */
+SDTW_API int sdtw_forward_u8(const float *queries, const int32_t *h_query_lens,
+                    const int32_t *query_lens, int32_t batch,
+                    const float *reference, int64_t ref_len,
+                    uint32_t *cost_codes, int64_t *end_pos, float *codebook,
+                    int32_t variant, void *workspace, size_t workspace_bytes, void *stream);
+
 SDTW_API int sdtw_forward_pruned(const float *queries, const int32_t *h_query_lens,
                         const int32_t *query_lens, int32_t batch,
                         const float *reference, int64_t ref_len, float prune_tau,

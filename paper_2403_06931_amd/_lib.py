@@ -59,6 +59,11 @@ def _load():
                                         ctypes.c_float, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                         _vp, ctypes.c_size_t, _vp]
     lib.sdtw_forward_pruned.restype = ctypes.c_int
+    lib.sdtw_forward_u8_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64]
+    lib.sdtw_forward_u8_workspace_bytes.restype = ctypes.c_size_t
+    lib.sdtw_forward_u8.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _vp,
+                                    _vp, _vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
+    lib.sdtw_forward_u8.restype = ctypes.c_int
     lib.sdtw_backward_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64,
                                                   ctypes.c_int32]
     lib.sdtw_backward_workspace_bytes.restype = ctypes.c_size_t

@@ -159,6 +159,47 @@ def sdtw_forward_pruned(queries: torch.Tensor, h_query_lens, query_lens: torch.T
     return cost, end_pos
 
 
+def sdtw_forward_u8_workspace_bytes(h_query_lens, ref_len: int) -> int:
+    h = _host_lens(h_query_lens)
+    return int(_lib.lib.sdtw_forward_u8_workspace_bytes(_hp(h), h.size, int(ref_len)))
+
+
+def sdtw_forward_u8(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
+                    reference: torch.Tensor, *,
+                    cost_codes: Optional[torch.Tensor] = None,
+                    end_pos: Optional[torch.Tensor] = None,
+                    codebook: Optional[torch.Tensor] = None,
+                    variant: int = -1,
+                    workspace_buf: Optional[torch.Tensor] = None,
+                    stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Forward on uint8 codes (codebook from the reference, integer DP) ->
+    (cost_codes int32 [B] holding the uint32 minimum in step^2 units,
+    end_pos int64 [B], codebook float32 [2] = lo, hi)."""
+    h = _host_lens(h_query_lens)
+    _require_cuda("queries", queries, torch.float32)
+    _require_cuda("query_lens", query_lens, torch.int32)
+    _require_cuda("reference", reference, torch.float32)
+    dev = queries.device
+    b = h.size
+    if cost_codes is None:
+        cost_codes = torch.empty(b, dtype=torch.int32, device=dev)
+    if end_pos is None:
+        end_pos = torch.empty(b, dtype=torch.int64, device=dev)
+    if codebook is None:
+        codebook = torch.empty(2, dtype=torch.float32, device=dev)
+    need = sdtw_forward_u8_workspace_bytes(h, reference.numel())
+    if need == 0:
+        raise SdtwError(_lib.SDTW_ERR_INVALID_ARG, "sdtw_forward_u8_workspace_bytes")
+    if workspace_buf is None:
+        workspace_buf = workspace(need, dev)
+    st = _lib.lib.sdtw_forward_u8(
+        _dp(queries), _hp(h), _dp(query_lens), b, _dp(reference), reference.numel(),
+        _dp(cost_codes), _dp(end_pos), _dp(codebook), int(variant), _dp(workspace_buf),
+        workspace_buf.numel(), _stream(stream))
+    check(st, "sdtw_forward_u8")
+    return cost_codes, end_pos, codebook
+
+
 def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
                   reference: torch.Tensor, cost_kind: int, grad_cost: torch.Tensor,
                   cost: torch.Tensor, end_pos: torch.Tensor, ckpt: Optional[torch.Tensor],

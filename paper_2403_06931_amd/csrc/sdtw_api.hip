@@ -12,6 +12,7 @@
 #include "sdtw_argmin.hpp"
 #include "sdtw_bwd.hpp"
 #include "sdtw_fwd.hpp"
+#include "sdtw_quant.hpp"
 #include "sdtw_setup.hpp"
 #include "sdtw_variant.hpp"
 #include "sdtw_znorm.hpp"
@@ -94,6 +95,34 @@ FwdLayout fwd_layout(int32_t batch, int64_t ref_len, int32_t flags, int64_t slot
   L.total = at;
   return L;
 }
+
+// uint8-code forward: the plain forward's workspace, then the codes of the
+// queries and of the reference, the per-chunk extremes and the codebook.
+struct U8Layout {
+  FwdLayout fwd;
+  size_t qcodes, rcodes, part, book, total;
+  int nparts;
+};
+
+U8Layout u8_layout(int32_t batch, int64_t total_rows, int64_t ref_len) {
+  U8Layout L{};
+  L.fwd = fwd_layout(batch, ref_len, 0, batch);
+  size_t at = L.fwd.total;
+  L.qcodes = at;
+  at = align_up(at + (size_t)total_rows, kAlign);
+  L.rcodes = at;
+  at = align_up(at + (size_t)ref_len, kAlign);
+  L.nparts = (int)((ref_len + sdtw::kQChunk - 1) / sdtw::kQChunk);
+  L.part = at;
+  at = align_up(at + sizeof(float2) * (size_t)L.nparts, kAlign);
+  L.book = at;
+  at = align_up(at + sizeof(sdtw::QBook), kAlign);
+  L.total = at;
+  return L;
+}
+
+constexpr int32_t kU8MaxRows = 32768;   // integer DP values stay below 0x7f800000
+constexpr int kU8Codes = 3;             // forward_impl's kind for the code DP
 
 int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
   if (every < 1) return -1;
@@ -455,6 +484,10 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
   } else {
     p.offsets = nullptr;            // each workgroup sums the lengths before its query
   }
+  if (cost_kind == kU8Codes) {
+    void* args[] = {(void*)&p};
+    return launch(v.u8, dim3(batch), dim3(64 * v.W), args, stream);
+  }
   if (persistent) {
     int32_t* order = reinterpret_cast<int32_t*>(ws + L.order);
     int32_t* queue = reinterpret_cast<int32_t*>(ws + L.queue);
@@ -499,6 +532,70 @@ int sdtw_forward_pruned(const float* queries, const int32_t* h_query_lens,
   return forward_impl(queries, h_query_lens, query_lens, batch, reference, ref_len,
                       sdtw::kPruned, prune_tau, cost, end_pos, nullptr, 0, variant_id, flags,
                       workspace, workspace_bytes, stream_ptr);
+}
+
+size_t sdtw_forward_u8_workspace_bytes(const int32_t* h_query_lens, int32_t batch,
+                                       int64_t ref_len) {
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len)) return 0;
+  if (nmax > kU8MaxRows) return 0;
+  return u8_layout(batch, total, ref_len).total;
+}
+
+int sdtw_forward_u8(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
+                    int32_t batch, const float* reference, int64_t ref_len, uint32_t* cost_codes,
+                    int64_t* end_pos, float* codebook, int32_t variant_id, void* workspace,
+                    size_t workspace_bytes, void* stream_ptr) {
+  int64_t total = 0;
+  int32_t nmax = 0;
+  if (!queries || !query_lens || !reference || !cost_codes || !end_pos || !codebook ||
+      !workspace)
+    return SDTW_ERR_INVALID_ARG;
+  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
+    return SDTW_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  if (nmax > kU8MaxRows) return SDTW_ERR_UNSUPPORTED;
+  if (variant_id < -1 || variant_id >= variant_count()) return SDTW_ERR_UNSUPPORTED;
+  const U8Layout L = u8_layout(batch, total, ref_len);
+  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
+  char* ws = static_cast<char*>(workspace);
+  uint8_t* qcodes = reinterpret_cast<uint8_t*>(ws + L.qcodes);
+  uint8_t* rcodes = reinterpret_cast<uint8_t*>(ws + L.rcodes);
+  float2* part = reinterpret_cast<float2*>(ws + L.part);
+  sdtw::QBook* book = reinterpret_cast<sdtw::QBook*>(ws + L.book);
+  {
+    void* args[] = {(void*)&reference, (void*)&ref_len, (void*)&part};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_u8_minmax_kernel), dim3(L.nparts),
+                    dim3(sdtw::kQThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  {
+    int nparts = L.nparts;
+    void* args[] = {(void*)&part, (void*)&nparts, (void*)&book, (void*)&codebook};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_u8_book_kernel), dim3(1),
+                    dim3(sdtw::kQThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  const struct { const float* x; int64_t n; uint8_t* c; } enc[2] = {
+      {queries, total, qcodes}, {reference, ref_len, rcodes}};
+  for (const auto& e : enc) {
+    const float* x = e.x;
+    int64_t n = e.n;
+    uint8_t* c = e.c;
+    const int grid = (int)std::min<int64_t>((n + sdtw::kQThreads - 1) / sdtw::kQThreads, 8192);
+    void* args[] = {(void*)&x, (void*)&n, (void*)&book, (void*)&c};
+    int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_u8_encode_kernel), dim3(grid),
+                    dim3(sdtw::kQThreads), args, stream);
+    if (rc != SDTW_OK) return rc;
+  }
+  // The DP itself: the plain forward over the codes (one byte per element).
+  // Its cost output receives the integer minimum's 32 bits.
+  return forward_impl(reinterpret_cast<const float*>(qcodes), h_query_lens, query_lens, batch,
+                      reinterpret_cast<const float*>(rcodes), ref_len, kU8Codes, 0.0f,
+                      reinterpret_cast<float*>(cost_codes), end_pos, nullptr, 0, variant_id, 0,
+                      workspace, L.fwd.total, stream_ptr);
 }
 
 size_t sdtw_forward_f16_workspace_bytes(const int32_t* h_query_lens, int32_t batch,

@@ -98,17 +98,19 @@ template <int R, int T, int W, int KS, int XL, typename V = float>
 struct Stager {
   using S = FwdShape<R, T, W, KS, XL>;
   static constexpr int PER = (S::CHUNK + S::THREADS - 1) / S::THREADS;
-  float ref[PER];
+  using In = typename Val<V>::In;
+  In ref[PER];
   V top[PER];
 
-  __device__ __forceinline__ void load(const float* __restrict__ reference, int ref_len,
+  __device__ __forceinline__ void load(const float* __restrict__ reference_in, int ref_len,
                                        const V* __restrict__ prev_row, int row_len,
                                        int tile0, int tid) {
+    const In* __restrict__ reference = reinterpret_cast<const In*>(reference_in);
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = tid + u * S::THREADS;
       const int j = tile0 * T + e;
-      float rv = 0.0f;
+      In rv = In(0);
       V tv = Val<V>::zero();
       if (e < S::CHUNK) {
         if (j < ref_len) rv = reference[j];
@@ -436,9 +438,10 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   G.qoff = qoff;
   G.row = row;
   G.s_out = reinterpret_cast<float*>(s_slot + S0::SLOTS);
-  const float* __restrict__ q = p.queries + qoff;
+  using In = typename Val<V>::In;
+  const In* __restrict__ q = reinterpret_cast<const In*>(p.queries) + qoff;
   // second query of a binary16 pair (the same one at the end of an odd batch)
-  const float* __restrict__ q2 = (Val<V>::N > 1 && b + 1 < p.batch) ? q + G.n : q;
+  const In* __restrict__ q2 = (Val<V>::N > 1 && b + 1 < p.batch) ? q + G.n : q;
   G.ntiles = (p.ref_len + T - 1) / T;
   const int npass = (G.n + S::ROWS - 1) / S::ROWS;
   const int steps = G.ntiles + S::LL * (kWave * W - 1) + (W - 1) * S::LAG;
@@ -457,7 +460,7 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     for (int k = 0; k < R; ++k) {
       const bool in = G.row0 + k < G.n;
       if constexpr (Val<V>::N == 1) {
-        L.qv[k] = in ? q[G.row0 + k] : 0.0f;
+        L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : In(0), In(0));
       } else {
         L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : 0.0f, in ? q2[G.row0 + k] : 0.0f);
       }
@@ -494,6 +497,9 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     // see +inf), then the first two intervals of reference and top boundary.
     for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
     for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
+    if constexpr (Val<V>::kZeroRing) {
+      for (int e = tid; e < S::SR * T; e += S::THREADS) s_ref[e] = Val<V>::zero();
+    }
     __syncthreads();
     {
       Stager<R, T, W, KS, XL, V> st0, st1;
@@ -562,6 +568,17 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd16_kernel(const FwdParams p
   const int b = 2 * (int)blockIdx.x;
   float* row = p.rowbuf + (int64_t)blockIdx.x * p.row_stride;
   fwd_query<R, T, W, KS, XL, KIND, false, f16x2>(p, b, query_offset(p, b), row, s_mem);
+}
+
+// uint8-code form (integer DP on quantised values): one workgroup per query;
+// queries and reference hold one code byte per element.
+template <int R, int T, int W, int KS, int XL>
+__global__ __launch_bounds__(kWave * W) void sdtw_fwd_u8_kernel(const FwdParams p) {
+  using S = FwdShape<R, T, W, KS, XL>;
+  __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
+  const int b = blockIdx.x;
+  float* row = p.rowbuf + (int64_t)b * p.row_stride;
+  fwd_query<R, T, W, KS, XL, kSquared, false, uint32_t>(p, b, query_offset(p, b), row, s_mem);
 }
 
 // Persistent form: a fixed grid pops queries (in the given order, longest

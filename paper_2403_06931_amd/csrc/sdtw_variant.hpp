@@ -1,6 +1,6 @@
 // sdtw_variant.hpp -- one compiled forward tile variant: its shape and the
-// kernel entry points for each cost kind and checkpoint mode, its pruned
-// form and its binary16 form.
+// kernel entry points for each cost kind and checkpoint mode, its pruned,
+// binary16 and uint8-code forms.
 #pragma once
 
 #include "sdtw_fwd.hpp"
@@ -13,6 +13,7 @@ struct Variant {
   const void* persistent[2][2];
   const void* half[2];            // [cost kind]: binary16, two queries per lane row
   const void* pruned[2];          // squared cost with early pruning: [plain, persistent]
+  const void* u8;                 // integer DP on uint8 codes
   int lds_bytes;
 };
 
@@ -34,6 +35,7 @@ Variant make_variant() {
   v.persistent[1][1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, 1, true>);
   v.pruned[0] = reinterpret_cast<const void*>(&sdtw_fwd_kernel<R, T, W, KS, XL, kPruned, false>);
   v.pruned[1] = reinterpret_cast<const void*>(&sdtw_fwd_persistent_kernel<R, T, W, KS, XL, kPruned, false>);
+  v.u8 = reinterpret_cast<const void*>(&sdtw_fwd_u8_kernel<R, T, W, KS, XL>);
   v.half[0] = reinterpret_cast<const void*>(&sdtw_fwd16_kernel<R, T, W, KS, XL, 0>);
   v.half[1] = reinterpret_cast<const void*>(&sdtw_fwd16_kernel<R, T, W, KS, XL, 1>);
   v.lds_bytes = (int)(sizeof(float) * FwdShape<R, T, W, KS, XL>::LDS_FLOATS);

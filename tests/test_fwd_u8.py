@@ -1,0 +1,93 @@
+"""GPU parity of the uint8-code forward (sdtw_forward_u8: codebook from the
+reference, codes of both sides, exact integer DP) against the quantisation
+oracle: identical codebook, bit-exact cost (in step^2 units) and end
+position, every compiled tile variant, ragged and degenerate shapes, values
+beyond the codebook's clip, and the full 512 x 2,000 vs 100,000 shape on
+sampled queries."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.quant as Q
+import workloads
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _variants():
+    import paper_2403_06931_amd as P
+    return list(range(P.sdtw_variant_count()))
+
+
+def _gpu_u8(w, variant=-1):
+    import paper_2403_06931_amd as P
+    q, l, r = to_dev(w)
+    cost, end, book = P.sdtw_forward_u8(q, w.lens, l, r, variant=variant)
+    torch.cuda.synchronize()
+    return (cost.cpu().numpy().view(np.uint32).astype(np.int64), end.cpu().numpy(),
+            tuple(book.cpu().numpy()))
+
+
+def _check(w, got, what, want=None):
+    want_c, want_e, (lo, hi) = Q.sdtw_u8(w.queries, w.lens, w.reference) if want is None else want
+    c, e, book = got
+    assert book == (lo, hi), (what, book, (lo, hi))
+    bad = np.nonzero((c != want_c) | (e != want_e))[0]
+    assert bad.size == 0, (f"{what}: {bad.size} mismatches, first {bad[:8].tolist()}: gpu "
+                           f"{c[bad[:8]].tolist()} {e[bad[:8]].tolist()} | oracle "
+                           f"{want_c[bad[:8]].tolist()} {want_e[bad[:8]].tolist()}")
+
+
+def test_u8_small_config_all_variants():
+    w = workloads.make_config(0)
+    for v in _variants():
+        print(f"u8 config 0 variant {v}", flush=True)
+        _check(w, _gpu_u8(w, v), f"u8 variant {v}")
+
+
+def test_u8_ragged_all_variants():
+    lens = [1, 5, 64, 65, 700, 2049, 4000, 300, 3]
+    w = workloads.make_random(len(lens), lens, 6001, seed=919)
+    for v in _variants():
+        print(f"u8 ragged variant {v}", flush=True)
+        _check(w, _gpu_u8(w, v), f"u8 ragged variant {v}")
+
+
+def test_u8_clipped_and_degenerate():
+    """Values scaled past the codebook's clip (end codes), queries longer than
+    a short reference, a one-sample reference and a constant one."""
+    lens = [50, 400, 1300]
+    w = workloads.make_random(len(lens), lens, 2000, seed=920)
+    ws = w.__class__(**{**w.__dict__, "queries": (w.queries * 3).astype(np.float32),
+                        "reference": (w.reference * 3).astype(np.float32)})
+    assert np.abs(ws.reference).max() > 4.0
+    for v in (-1, 1, 19):
+        print(f"u8 clipped variant {v}", flush=True)
+        _check(ws, _gpu_u8(ws, v), f"u8 clipped variant {v}")
+    rng = np.random.default_rng(921)
+    for r in (workloads.random_walk(rng, 300), np.zeros(1), np.full(64, 0.25)):
+        wr = w.__class__(**{**w.__dict__, "reference": np.asarray(r, np.float32)})
+        print(f"u8 reference of {wr.ref_len}", flush=True)
+        _check(wr, _gpu_u8(wr), f"u8 reference {wr.ref_len}")
+
+
+def test_u8_full_size_sampled():
+    """512 x 2,000 vs 100,000 in the library's choice and in the tile the
+    benchmark's headline uses; 8 sampled queries against the oracle (with the
+    codebook of the whole reference)."""
+    w = workloads.make_config(1)
+    idx = workloads.subset_indices(w, 8, seed=14)
+    sub = w.subset(idx)
+    want = Q.sdtw_u8(sub.queries, sub.lens, w.reference)
+    for v in (-1, 1):
+        print(f"u8 full size variant {v}", flush=True)
+        c, e, book = _gpu_u8(w, v)
+        _check(sub, (c[idx], e[idx], book), f"u8 512x2000 variant {v}", want=want)
+
+
+def test_u8_rejects_queries_past_the_integer_bound():
+    import paper_2403_06931_amd as P
+    w = workloads.make_random(1, [40000], 50000, seed=922, excerpt_every=0)
+    with pytest.raises(P.SdtwError):
+        _gpu_u8(w)
