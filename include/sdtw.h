@@ -138,22 +138,6 @@ SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
                  void *workspace, size_t workspace_bytes, void *stream);
 
 /*
- * Forward pass with early pruning, the cost rule Section 8 proposes: after
- * the subtraction t = q_i - r_j, a pair with |t| > prune_tau is taken to be
- * unable to lie on the warp path and costs +inf (no multiplication);
- * otherwise the cost is t*t, as for SDTW_COST_SQUARED.  Everything else is
- * sdtw_forward's: the same DP, outputs, variants and workspace
- * (sdtw_forward_workspace_bytes with the same flags).  The result is an
- * approximation of the squared-cost sDTW: cost[b] >= the exact cost, equal
- * whenever some optimal path has every |t| <= prune_tau (always for
- * prune_tau = +inf); a query with no such path gets +inf and end_pos 0.
- *
- *   prune_tau  any float32 but NaN (NaN: SDTW_ERR_INVALID_ARG); a negative
- *              value prunes every pair
- *   flags      0 or SDTW_F_PERSISTENT (checkpoints: SDTW_ERR_INVALID_ARG)
- *   other arguments as for sdtw_forward
- */
-/*
  * Bytes of device workspace sdtw_forward_u8 needs: sdtw_forward's (no flags),
  * one byte per query and reference element for the codes, and the codebook.
  * Returns 0 on invalid arguments or when a query is longer than 32,768 rows.
@@ -170,16 +154,17 @@ SDTW_API size_t sdtw_forward_u8_workspace_bytes(const int32_t *h_query_lens, int
  *   lo = max(min(reference), -4),  hi = min(max(reference), 4),
  *   code(x) = clamp(rint((x - lo) * 255 / (hi - lo)), 0, 255)
  * in binary64, round half to even (every code 0 when hi <= lo).  The DP of
- * sdtw_forward then runs exactly in 32-bit integers on the codes with the
- * local cost (a - b)^2, so cost_codes * step^2, step = (hi - lo) / 255,
- * approximates the squared-cost sDTW of the original values.
+ * sdtw_forward then runs in binary32 on the codes taken as numbers 0..255
+ * with the local cost (a - b)^2 (exact: at most 65025), so cost is the
+ * binary32 DP of the codes -- exact integers while the sums stay below 2^24
+ * -- and cost * step^2, step = (hi - lo) / 255, approximates the
+ * squared-cost sDTW of the original values.
  *
  *   queries, h_query_lens, query_lens, batch, reference, ref_len, variant,
  *                stream: as for sdtw_forward; queries at most 32,768 rows
- *                (SDTW_ERR_UNSUPPORTED otherwise, which keeps every DP value
- *                below 2^31)
- *   cost_codes   device uint32 [batch]: minimum of the last row, in units of
- *                step^2 (output)
+ *                (SDTW_ERR_UNSUPPORTED otherwise)
+ *   cost         device float32 [batch]: minimum of the last row, in units
+ *                of step^2 (output)
  *   end_pos      device int64 [batch], 0-based, first minimiser (output)
  *   codebook     device float32 [2]: lo, hi (output)
  *   workspace    device, >= sdtw_forward_u8_workspace_bytes(...) bytes,
@@ -188,9 +173,25 @@ SDTW_API size_t sdtw_forward_u8_workspace_bytes(const int32_t *h_query_lens, int
 SDTW_API int sdtw_forward_u8(const float *queries, const int32_t *h_query_lens,
                     const int32_t *query_lens, int32_t batch,
                     const float *reference, int64_t ref_len,
-                    uint32_t *cost_codes, int64_t *end_pos, float *codebook,
+                    float *cost, int64_t *end_pos, float *codebook,
                     int32_t variant, void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * Forward pass with early pruning, the cost rule Section 8 proposes: after
+ * the subtraction t = q_i - r_j, a pair with |t| > prune_tau is taken to be
+ * unable to lie on the warp path and costs +inf (no multiplication);
+ * otherwise the cost is t*t, as for SDTW_COST_SQUARED.  Everything else is
+ * sdtw_forward's: the same DP, outputs, variants and workspace
+ * (sdtw_forward_workspace_bytes with the same flags).  The result is an
+ * approximation of the squared-cost sDTW: cost[b] >= the exact cost, equal
+ * whenever some optimal path has every |t| <= prune_tau (always for
+ * prune_tau = +inf); a query with no such path gets +inf and end_pos 0.
+ *
+ *   prune_tau  any float32 but NaN (NaN: SDTW_ERR_INVALID_ARG); a negative
+ *              value prunes every pair
+ *   flags      0 or SDTW_F_PERSISTENT (checkpoints: SDTW_ERR_INVALID_ARG)
+ *   other arguments as for sdtw_forward
+ */
 SDTW_API int sdtw_forward_pruned(const float *queries, const int32_t *h_query_lens,
                         const int32_t *query_lens, int32_t batch,
                         const float *reference, int64_t ref_len, float prune_tau,

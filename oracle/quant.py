@@ -11,12 +11,14 @@ values within ``CLIP`` = 4 standard deviations of the mean; the codebook is
 256 evenly spaced levels from lo = max(min(reference), -4) to
 hi = min(max(reference), 4); a value's code is the nearest level, computed as
 clamp(rint((x - lo) * 255 / (hi - lo)), 0, 255) in binary64 with ties to
-even, and every code is 0 when hi <= lo.  The DP on the codes is
-``oracle.sdtw_codes`` (plain C, exact integers).
+even, and every code is 0 when hi <= lo.  The DP on the codes is the
+binary32 DP of ``oracle.sdtw_f32`` applied to the codes as numbers 0..255 with
+the squared cost (each cost (a - b)^2 <= 65025 is exact; the sums are exact
+integers below 2^24); ``oracle.sdtw_codes`` is its exact-integer twin.
 """
 import numpy as np
 
-from . import sdtw_codes
+from . import SQUARED, sdtw_f32
 
 CLIP = np.float32(4.0)
 
@@ -38,8 +40,10 @@ def encode(x, lo, hi):
 
 
 def sdtw_u8(queries, lens, reference, nthreads=0):
-    """Codebook from the reference, codes of both sides, integer sDTW ->
-    (cost int64 [B] in step^2 units, end_pos int64 [B], (lo, hi))."""
+    """Codebook from the reference, codes of both sides, binary32 sDTW of the
+    codes -> (cost float32 [B] in step^2 units, end_pos int64 [B], (lo, hi))."""
     lo, hi = codebook(reference)
-    cost, end = sdtw_codes(encode(queries, lo, hi), lens, encode(reference, lo, hi), nthreads)
+    qc = encode(queries, lo, hi).astype(np.float32)
+    rc = encode(reference, lo, hi).astype(np.float32)
+    cost, end = sdtw_f32(qc, lens, rc, SQUARED, nthreads)
     return cost, end, (lo, hi)

@@ -606,9 +606,9 @@ int64_t oracle_sdtw_path_f32(const float *q, int32_t n, const float *ref,
 }
 
 /* ------------------------------------------------------------------ */
-/* sDTW on uint8 codes (Section 8's proposed quantisation): the same    */
-/* recurrence, with the local cost (a - b)^2 of two codes, in exact     */
-/* integer arithmetic.                                                  */
+/* sDTW on uint8 codes (Section 8's proposed quantisation) in exact     */
+/* integer arithmetic, local cost (a - b)^2: the twin that pins the     */
+/* binary32 DP of the codes while its sums stay below 2^24.             */
 /* ------------------------------------------------------------------ */
 
 static void sdtw_one_codes(const uint8_t *q, int64_t n, const uint8_t *r, int64_t m,

@@ -166,23 +166,23 @@ def sdtw_forward_u8_workspace_bytes(h_query_lens, ref_len: int) -> int:
 
 def sdtw_forward_u8(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
                     reference: torch.Tensor, *,
-                    cost_codes: Optional[torch.Tensor] = None,
+                    cost: Optional[torch.Tensor] = None,
                     end_pos: Optional[torch.Tensor] = None,
                     codebook: Optional[torch.Tensor] = None,
                     variant: int = -1,
                     workspace_buf: Optional[torch.Tensor] = None,
                     stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
-    """Forward on uint8 codes (codebook from the reference, integer DP) ->
-    (cost_codes int32 [B] holding the uint32 minimum in step^2 units,
-    end_pos int64 [B], codebook float32 [2] = lo, hi)."""
+    """Forward on uint8 codes (codebook from the reference, binary32 DP of the
+    codes) -> (cost float32 [B] in step^2 units, end_pos int64 [B],
+    codebook float32 [2] = lo, hi)."""
     h = _host_lens(h_query_lens)
     _require_cuda("queries", queries, torch.float32)
     _require_cuda("query_lens", query_lens, torch.int32)
     _require_cuda("reference", reference, torch.float32)
     dev = queries.device
     b = h.size
-    if cost_codes is None:
-        cost_codes = torch.empty(b, dtype=torch.int32, device=dev)
+    if cost is None:
+        cost = torch.empty(b, dtype=torch.float32, device=dev)
     if end_pos is None:
         end_pos = torch.empty(b, dtype=torch.int64, device=dev)
     if codebook is None:
@@ -194,10 +194,10 @@ def sdtw_forward_u8(queries: torch.Tensor, h_query_lens, query_lens: torch.Tenso
         workspace_buf = workspace(need, dev)
     st = _lib.lib.sdtw_forward_u8(
         _dp(queries), _hp(h), _dp(query_lens), b, _dp(reference), reference.numel(),
-        _dp(cost_codes), _dp(end_pos), _dp(codebook), int(variant), _dp(workspace_buf),
+        _dp(cost), _dp(end_pos), _dp(codebook), int(variant), _dp(workspace_buf),
         workspace_buf.numel(), _stream(stream))
     check(st, "sdtw_forward_u8")
-    return cost_codes, end_pos, codebook
+    return cost, end_pos, codebook
 
 
 def sdtw_backward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,

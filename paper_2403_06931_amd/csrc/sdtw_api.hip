@@ -121,7 +121,7 @@ U8Layout u8_layout(int32_t batch, int64_t total_rows, int64_t ref_len) {
   return L;
 }
 
-constexpr int32_t kU8MaxRows = 32768;   // integer DP values stay below 0x7f800000
+constexpr int32_t kU8MaxRows = 32768;   // a documented bound on query length for codes
 constexpr int kU8Codes = 3;             // forward_impl's kind for the code DP
 
 int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
@@ -544,12 +544,12 @@ size_t sdtw_forward_u8_workspace_bytes(const int32_t* h_query_lens, int32_t batc
 }
 
 int sdtw_forward_u8(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
-                    int32_t batch, const float* reference, int64_t ref_len, uint32_t* cost_codes,
+                    int32_t batch, const float* reference, int64_t ref_len, float* cost,
                     int64_t* end_pos, float* codebook, int32_t variant_id, void* workspace,
                     size_t workspace_bytes, void* stream_ptr) {
   int64_t total = 0;
   int32_t nmax = 0;
-  if (!queries || !query_lens || !reference || !cost_codes || !end_pos || !codebook ||
+  if (!queries || !query_lens || !reference || !cost || !end_pos || !codebook ||
       !workspace)
     return SDTW_ERR_INVALID_ARG;
   if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
@@ -591,11 +591,10 @@ int sdtw_forward_u8(const float* queries, const int32_t* h_query_lens, const int
     if (rc != SDTW_OK) return rc;
   }
   // The DP itself: the plain forward over the codes (one byte per element).
-  // Its cost output receives the integer minimum's 32 bits.
   return forward_impl(reinterpret_cast<const float*>(qcodes), h_query_lens, query_lens, batch,
                       reinterpret_cast<const float*>(rcodes), ref_len, kU8Codes, 0.0f,
-                      reinterpret_cast<float*>(cost_codes), end_pos, nullptr, 0, variant_id, 0,
-                      workspace, L.fwd.total, stream_ptr);
+                      cost, end_pos, nullptr, 0, variant_id, 0, workspace, L.fwd.total,
+                      stream_ptr);
 }
 
 size_t sdtw_forward_f16_workspace_bytes(const int32_t* h_query_lens, int32_t batch,

@@ -253,9 +253,7 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
     V cur[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t], L.tau);
-      const V mn = Val<V>::min3(up[t], left, diag);
-      cur[t] = Val<V>::add(mn, c);
+      cur[t] = Val<V>::template cell<KIND>(L.qv[k], rv[t], up[t], left, diag, L.tau);
       diag = up[t];
       left = cur[t];
     }
@@ -497,9 +495,6 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     // see +inf), then the first two intervals of reference and top boundary.
     for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
     for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
-    if constexpr (Val<V>::kZeroRing) {
-      for (int e = tid; e < S::SR * T; e += S::THREADS) s_ref[e] = Val<V>::zero();
-    }
     __syncthreads();
     {
       Stager<R, T, W, KS, XL, V> st0, st1;
@@ -578,7 +573,7 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_u8_kernel(const FwdParams 
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   const int b = blockIdx.x;
   float* row = p.rowbuf + (int64_t)b * p.row_stride;
-  fwd_query<R, T, W, KS, XL, kSquared, false, uint32_t>(p, b, query_offset(p, b), row, s_mem);
+  fwd_query<R, T, W, KS, XL, kSquared, false, Code8>(p, b, query_offset(p, b), row, s_mem);
 }
 
 // Persistent form: a fixed grid pops queries (in the given order, longest

@@ -9,10 +9,8 @@
 //           of equal length, so both halves see the same reference value
 //           and the same neighbours: every packed operation does two cells
 //           of unrelated DPs, with no shuffling between halves.
-//   uint32_t  one query per lane row, on uint8 codes (Section 8's proposed
-//           quantisation): the local cost (a - b)^2 and the DP run exactly in
-//           32-bit integers (v_sub_u32, v_mul_i32_i24, v_min3_u32, v_add_u32,
-//           all full-rate and dual-issuable like their binary32 twins).
+//   Code8   one query per lane row, on uint8 codes (Section 8's proposed
+//           quantisation), the DP in binary32 with the local cost (a - b)^2.
 //
 // Each packed operation rounds each half to nearest-even binary16, with
 // subnormals kept; the minimum is exact.
@@ -32,7 +30,6 @@ template <>
 struct Val<float> {
   using In = float;                            // element type in HBM
   static constexpr int N = 1;                  // queries per value
-  static constexpr bool kZeroRing = false;     // +inf absorbs any cost
   __device__ static float inf() { return inf_f32(); }
   __device__ static float zero() { return 0.0f; }
   __device__ static float query(float a, float) { return a; }
@@ -41,6 +38,11 @@ struct Val<float> {
   __device__ static float cost(float q, float r, float tau) { return local_cost<KIND>(q, r, tau); }
   __device__ static float min3(float a, float b, float c) { return sdtw::min3(a, b, c); }
   __device__ static float add(float a, float b) { return a + b; }
+  template <int KIND>
+  __device__ static float cell(float q, float r, float up, float left, float diag, float tau) {
+    const float c = cost<KIND>(q, r, tau);
+    return min3(up, left, diag) + c;
+  }
   __device__ static float shr1(float lane0, float v) { return wave_shr1(lane0, v); }
   __device__ static float half(float v, int) { return v; }
 };
@@ -49,7 +51,6 @@ template <>
 struct Val<f16x2> {
   using In = float;
   static constexpr int N = 2;
-  static constexpr bool kZeroRing = false;
   __device__ static f16x2 inf() {
     const _Float16 h = (_Float16)__builtin_huge_valf();
     return f16x2{h, h};
@@ -92,43 +93,35 @@ struct Val<f16x2> {
   __device__ static float half(f16x2 v, int h) { return (float)(h == 0 ? v.x : v.y); }
 };
 
-// Integer DP on codes.  "Infinity" is 0x7f800000, the bit pattern of
-// binary32 +inf: below it, non-negative 32-bit integers order like the
-// binary32 values with the same bits, so the last-row fold and its result
-// move through the binary32 paths unchanged.  Every computed cell of a query
-// of n rows is at most n * 255^2 (the path down the diagonal or a column), so
-// finite values stay below 0x7f800000 for n <= 32,768.  Cells that the
-// schedule computes before a lane's first real tile start from the boundary
-// value and only grow, so they never undercut a real one -- provided every
-// local cost stays at most 255^2: the reference ring is zeroed before each
-// pass (kZeroRing), since an unwritten slot read by such a cell would give an
-// arbitrary 32-bit product and a sum that wraps.  With costs bounded, those
-// cells grow by at most 255^2 per column over a fill of at most ~10^4
-// columns, far from wrapping past 2^32.
+// DP on uint8 codes, in binary32.  A code difference is an integer of at
+// most 255 in magnitude, so t*t <= 65025 is exact in binary32 and one fused
+// multiply-add, D = fma(t, t, min3), rounds exactly like the separate
+// product and sum: the cell is three binary32 instructions (v_sub_f32,
+// v_min3_f32, v_fma_f32), all of which can dual-issue, and the values equal
+// the binary32 DP of the codes taken as floats (exact integers while the
+// sums stay below 2^24).  +inf absorbs as in the binary32 path.
+struct Code8 {
+  float v;
+};
+
 template <>
-struct Val<uint32_t> {
+struct Val<Code8> {
   using In = uint8_t;
   static constexpr int N = 1;
-  static constexpr bool kZeroRing = true;
-  __device__ static uint32_t inf() { return 0x7f800000u; }
-  __device__ static uint32_t zero() { return 0u; }
-  __device__ static uint32_t query(uint8_t a, uint8_t) { return a; }
-  __device__ static uint32_t ref(uint8_t r) { return r; }
+  __device__ static Code8 inf() { return Code8{inf_f32()}; }
+  __device__ static Code8 zero() { return Code8{0.0f}; }
+  __device__ static Code8 query(uint8_t a, uint8_t) { return Code8{(float)a}; }
+  __device__ static Code8 ref(uint8_t r) { return Code8{(float)r}; }
   template <int KIND>
-  __device__ static uint32_t cost(uint32_t q, uint32_t r, float) {
+  __device__ static Code8 cell(Code8 q, Code8 r, Code8 up, Code8 left, Code8 diag, float) {
     static_assert(KIND == kSquared, "codes use the squared difference");
-    const int t = (int)q - (int)r;               // |t| <= 255: a 24-bit product
-    return (uint32_t)__mul24(t, t);
+    const float t = q.v - r.v;                   // exact
+    return Code8{__builtin_fmaf(t, t, sdtw::min3(up.v, left.v, diag.v))};
   }
-  __device__ static uint32_t min3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_elementwise_min(__builtin_elementwise_min(a, b), c);
+  __device__ static Code8 shr1(Code8 lane0, Code8 v) {
+    return Code8{wave_shr1(lane0.v, v.v)};
   }
-  __device__ static uint32_t add(uint32_t a, uint32_t b) { return a + b; }
-  __device__ static uint32_t shr1(uint32_t lane0, uint32_t v) {
-    return __builtin_bit_cast(
-        uint32_t, wave_shr1(__builtin_bit_cast(float, lane0), __builtin_bit_cast(float, v)));
-  }
-  __device__ static float half(uint32_t v, int) { return __builtin_bit_cast(float, v); }
+  __device__ static float half(Code8 v, int) { return v.v; }
 };
 
 }  // namespace sdtw

@@ -1,7 +1,7 @@
 """GPU parity of the uint8-code forward (sdtw_forward_u8: codebook from the
 reference, codes of both sides, exact integer DP) against the quantisation
-oracle: identical codebook, bit-exact cost (in step^2 units) and end
-position, every compiled tile variant, ragged and degenerate shapes, values
+oracle (the binary32 DP of the codes): identical codebook, bit-exact cost (in
+step^2 units) and end position, every compiled tile variant, ragged and degenerate shapes, values
 beyond the codebook's clip, and the full 512 x 2,000 vs 100,000 shape on
 sampled queries."""
 import numpy as np
@@ -25,15 +25,14 @@ def _gpu_u8(w, variant=-1):
     q, l, r = to_dev(w)
     cost, end, book = P.sdtw_forward_u8(q, w.lens, l, r, variant=variant)
     torch.cuda.synchronize()
-    return (cost.cpu().numpy().view(np.uint32).astype(np.int64), end.cpu().numpy(),
-            tuple(book.cpu().numpy()))
+    return cost.cpu().numpy(), end.cpu().numpy(), tuple(book.cpu().numpy())
 
 
 def _check(w, got, what, want=None):
     want_c, want_e, (lo, hi) = Q.sdtw_u8(w.queries, w.lens, w.reference) if want is None else want
     c, e, book = got
     assert book == (lo, hi), (what, book, (lo, hi))
-    bad = np.nonzero((c != want_c) | (e != want_e))[0]
+    bad = np.nonzero((c.view(np.uint32) != want_c.view(np.uint32)) | (e != want_e))[0]
     assert bad.size == 0, (f"{what}: {bad.size} mismatches, first {bad[:8].tolist()}: gpu "
                            f"{c[bad[:8]].tolist()} {e[bad[:8]].tolist()} | oracle "
                            f"{want_c[bad[:8]].tolist()} {want_e[bad[:8]].tolist()}")
@@ -65,6 +64,17 @@ def test_u8_clipped_and_degenerate():
     for v in (-1, 1, 19):
         print(f"u8 clipped variant {v}", flush=True)
         _check(ws, _gpu_u8(ws, v), f"u8 clipped variant {v}")
+    # a query alternating between the end codes: sums pass 2^24, so the
+    # binary32 DP of the codes rounds (both sides identically)
+    alt = np.tile(np.array([-10.0, 10.0], np.float32), 2000)
+    rng = np.random.default_rng(923)
+    wa = w.__class__(**{**w.__dict__, "queries": alt, "lens": np.array([4000], np.int32),
+                        "reference": workloads.random_walk(rng, 3000).astype(np.float32),
+                        "excerpt_start": np.array([-1], np.int64)})
+    want = Q.sdtw_u8(wa.queries, wa.lens, wa.reference)
+    assert want[0][0] > 2 ** 24
+    print("u8 alternating end codes", flush=True)
+    _check(wa, _gpu_u8(wa), "u8 sums past 2^24", want=want)
     rng = np.random.default_rng(921)
     for r in (workloads.random_walk(rng, 300), np.zeros(1), np.full(64, 0.25)):
         wr = w.__class__(**{**w.__dict__, "reference": np.asarray(r, np.float32)})

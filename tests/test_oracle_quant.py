@@ -6,13 +6,14 @@
 - codes: hand-worked values with a unit step (ties to even, clamping at both
   ends), and the nearest-level bound |lo + code * step - x| <= step / 2 for
   every value inside [lo, hi];
-- the integer DP on codes equals a pure-Python enumeration of all warp paths,
-  and equals the binary32 oracle run on the codes as floats (exact while the
-  sums stay below 2^24), which test_oracle_bruteforce.py pins on its own;
+- the exact-integer DP on codes equals a pure-Python enumeration of all warp
+  paths, and equals the binary32 DP of the codes (the quantised forward's
+  definition, pinned on its own by test_oracle_bruteforce.py) while the sums
+  stay below 2^24;
 - approximation: along the exact optimal path of the binary32 squared-cost
   DP, the coded costs sum to at least the code DP's minimum, and that sum is
   within the quantisation error of the path's exact cost, so
-  cost_codes * step^2 <= exact + sum over the path of step * (2|t| + step).
+  cost * step^2 <= exact + sum over the path of step * (2|t| + step).
 """
 import numpy as np
 import pytest
