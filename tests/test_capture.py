@@ -1,6 +1,7 @@
-"""The normaliser, the binary16 forward and the path output enqueue only
-kernels on the caller's stream and allocate nothing, so a HIP graph captures
-them: each replay (with eager work between replays) matches the eager call."""
+"""The normaliser, the binary16, pruned and uint8-code forwards and the path
+output enqueue only kernels on the caller's stream and allocate nothing, so a
+HIP graph captures them: each replay (with eager work between replays)
+matches the eager call."""
 import numpy as np
 import pytest
 import torch
@@ -84,3 +85,36 @@ def test_align_graph():
     g = _capture(run)
     s, lo, hi = res["out"]
     _replays(g, [s, lo, hi], [s0, lo0, hi0])
+
+
+def test_pruned_forward_graph():
+    """The pruned forward, plain and persistent (work queue reset inside the
+    captured sequence)."""
+    import paper_2403_06931_amd as P
+    w = workloads.make_random(12, [64, 700, 300, 2100] * 3, 3000, seed=6)
+    q, l, r = to_dev(w)
+    for flags in (0, P.SDTW_F_PERSISTENT):
+        ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags), q.device)
+        c = torch.empty(w.batch, dtype=torch.float32, device=q.device)
+        e = torch.empty(w.batch, dtype=torch.int64, device=q.device)
+        wc, we = P.sdtw_forward_pruned(q, w.lens, l, r, 1.5, flags=flags, workspace_buf=ws)
+        wc, we = wc.clone(), we.clone()
+        g = _capture(lambda: P.sdtw_forward_pruned(q, w.lens, l, r, 1.5, cost=c, end_pos=e,
+                                                   flags=flags, workspace_buf=ws))
+        _replays(g, [c, e], [wc, we])
+
+
+def test_u8_forward_graph():
+    """The uint8-code forward: codebook, codes and DP in one captured call."""
+    import paper_2403_06931_amd as P
+    w = workloads.make_random(8, [300] * 8, 4000, seed=7)
+    q, l, r = to_dev(w)
+    ws = P.workspace(P.sdtw_forward_u8_workspace_bytes(w.lens, w.ref_len), q.device)
+    c = torch.empty(w.batch, dtype=torch.float32, device=q.device)
+    e = torch.empty(w.batch, dtype=torch.int64, device=q.device)
+    b = torch.empty(2, dtype=torch.float32, device=q.device)
+    wc, we, wb = P.sdtw_forward_u8(q, w.lens, l, r, workspace_buf=ws)
+    wc, we, wb = wc.clone(), we.clone(), wb.clone()
+    g = _capture(lambda: P.sdtw_forward_u8(q, w.lens, l, r, cost=c, end_pos=e, codebook=b,
+                                           workspace_buf=ws))
+    _replays(g, [c, e, b], [wc, we, wb])
