@@ -140,7 +140,7 @@ SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
 /*
  * Bytes of device workspace sdtw_forward_u8 needs: sdtw_forward's (no flags),
  * one byte per query and reference element for the codes, and the codebook.
- * Returns 0 on invalid arguments or when a query is longer than 32,768 rows.
+ * Returns 0 on invalid arguments.
  */
 SDTW_API size_t sdtw_forward_u8_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
                                        int64_t ref_len);
@@ -161,8 +161,7 @@ SDTW_API size_t sdtw_forward_u8_workspace_bytes(const int32_t *h_query_lens, int
  * squared-cost sDTW of the original values.
  *
  *   queries, h_query_lens, query_lens, batch, reference, ref_len, variant,
- *                stream: as for sdtw_forward; queries at most 32,768 rows
- *                (SDTW_ERR_UNSUPPORTED otherwise)
+ *                stream: as for sdtw_forward
  *   cost         device float32 [batch]: minimum of the last row, in units
  *                of step^2 (output)
  *   end_pos      device int64 [batch], 0-based, first minimiser (output)

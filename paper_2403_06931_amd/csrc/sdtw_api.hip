@@ -121,7 +121,6 @@ U8Layout u8_layout(int32_t batch, int64_t total_rows, int64_t ref_len) {
   return L;
 }
 
-constexpr int32_t kU8MaxRows = 32768;   // a documented bound on query length for codes
 constexpr int kU8Codes = 3;             // forward_impl's kind for the code DP
 
 int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
@@ -537,9 +536,7 @@ int sdtw_forward_pruned(const float* queries, const int32_t* h_query_lens,
 size_t sdtw_forward_u8_workspace_bytes(const int32_t* h_query_lens, int32_t batch,
                                        int64_t ref_len) {
   int64_t total = 0;
-  int32_t nmax = 0;
-  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len)) return 0;
-  if (nmax > kU8MaxRows) return 0;
+  if (!lens_ok(h_query_lens, batch, &total, nullptr) || !ref_ok(ref_len)) return 0;
   return u8_layout(batch, total, ref_len).total;
 }
 
@@ -548,14 +545,12 @@ int sdtw_forward_u8(const float* queries, const int32_t* h_query_lens, const int
                     int64_t* end_pos, float* codebook, int32_t variant_id, void* workspace,
                     size_t workspace_bytes, void* stream_ptr) {
   int64_t total = 0;
-  int32_t nmax = 0;
   if (!queries || !query_lens || !reference || !cost || !end_pos || !codebook ||
       !workspace)
     return SDTW_ERR_INVALID_ARG;
-  if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
+  if (!lens_ok(h_query_lens, batch, &total, nullptr) || !ref_ok(ref_len))
     return SDTW_ERR_INVALID_ARG;
   if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
-  if (nmax > kU8MaxRows) return SDTW_ERR_UNSUPPORTED;
   if (variant_id < -1 || variant_id >= variant_count()) return SDTW_ERR_UNSUPPORTED;
   const U8Layout L = u8_layout(batch, total, ref_len);
   if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;

@@ -253,7 +253,7 @@ def test_forward_u8_validation(L):
     FAKE = 1 << 20
     h = np.ascontiguousarray([10, 12], dtype=np.int32)
     assert P.sdtw_forward_u8_workspace_bytes(h, 1000) > P.sdtw_forward_workspace_bytes(h, 1000)
-    assert P.sdtw_forward_u8_workspace_bytes(np.array([40000], np.int32), 1000) == 0
+    assert P.sdtw_forward_u8_workspace_bytes(np.array([40000], np.int32), 1000) > 0
     call = lambda hh=h, **k: L.lib.sdtw_forward_u8(
         _vp(k.get("q", FAKE)), _vp(hh.ctypes.data), _vp(FAKE), hh.size, _vp(FAKE), 100,
         _vp(k.get("c", FAKE)), _vp(FAKE), _vp(k.get("book", FAKE)), k.get("v", -1),
@@ -264,5 +264,4 @@ def test_forward_u8_validation(L):
     assert call(ws=FAKE + 4) == L.SDTW_ERR_INVALID_ARG
     assert call(wsb=16) == L.SDTW_ERR_WORKSPACE
     assert call(v=10_000) == L.SDTW_ERR_UNSUPPORTED
-    assert call(np.ascontiguousarray([40000], dtype=np.int32)) == L.SDTW_ERR_UNSUPPORTED
     assert call(np.ascontiguousarray([5, 0], dtype=np.int32)) == L.SDTW_ERR_INVALID_ARG

@@ -94,10 +94,3 @@ def test_u8_full_size_sampled():
         print(f"u8 full size variant {v}", flush=True)
         c, e, book = _gpu_u8(w, v)
         _check(sub, (c[idx], e[idx], book), f"u8 512x2000 variant {v}", want=want)
-
-
-def test_u8_rejects_queries_past_the_integer_bound():
-    import paper_2403_06931_amd as P
-    w = workloads.make_random(1, [40000], 50000, seed=922, excerpt_every=0)
-    with pytest.raises(P.SdtwError):
-        _gpu_u8(w)
