@@ -8,7 +8,10 @@
 //   vgpr  adds on vector registers only;
 //   cell  the DP cell of the sDTW kernels (t = a - r; c = t*t;
 //         d = min3(d, x, y) + c), vector registers only, at 1, 2, 4 and 8
-//         wavefronts per SIMD.
+//         wavefronts per SIMD;
+//   fma   fused multiply-adds on vector registers only;
+//   code  the cell of the uint8-code forward (t = a - r;
+//         d = fma(t, t, min3(d, x, y))), at 1, 2, 4 and 8 wavefronts per SIMD.
 // Run under rocprofv3 with SQ_INSTS_VALU and SQ_ACTIVE_INST_VALU2 to see the
 // share of instructions issued two per SIMD per quad-cycle.
 #include <hip/hip_runtime.h>
@@ -27,7 +30,8 @@
 constexpr int kIters = 4096;
 constexpr int kChains = 8;
 
-// mode 0: add with an SGPR operand; 1: add, VGPRs only; 2: DP cell, VGPRs only
+// mode 0: add with an SGPR operand; 1: add, VGPRs only; 2: DP cell, VGPRs only;
+// 3: fma, VGPRs only; 4: code cell (sub, min3, fma), VGPRs only
 template <int MODE>
 __global__ __launch_bounds__(256) void issue_kernel(float* out, const float* in, float s) {
   const int l = threadIdx.x & 31;
@@ -46,13 +50,18 @@ __global__ __launch_bounds__(256) void issue_kernel(float* out, const float* in,
         d[c] = d[c] + s;
       } else if constexpr (MODE == 1) {
         d[c] = d[c] + a[c];
+      } else if constexpr (MODE == 3) {
+        d[c] = __builtin_fmaf(a[c], x[c], d[c]);
+      } else if constexpr (MODE == 4) {
+        const float t = a[c] - r;
+        d[c] = __builtin_fmaf(t, t, __builtin_fminf(__builtin_fminf(d[c], x[c]), y));
       } else {
         const float t = a[c] - r;
         const float cc = t * t;
         d[c] = __builtin_fminf(__builtin_fminf(d[c], x[c]), y) + cc;
       }
     }
-    if constexpr (MODE == 2) r = r + y;
+    if constexpr (MODE == 2 || MODE == 4) r = r + y;
   }
   float acc = 0.f;
 #pragma unroll
@@ -77,7 +86,7 @@ int run(const char* name, int cus, int waves_per_simd, float* out, const float* 
     CHK(hipEventElapsedTime(&ms, a, b));
     if (ms < best) best = ms;
   }
-  const double per_iter = MODE == 2 ? kChains * 4 + 1 : kChains;
+  const double per_iter = MODE == 2 ? kChains * 4 + 1 : (MODE == 4 ? kChains * 3 + 1 : kChains);
   const double ops = (double)blocks * 256 * kIters * per_iter;
   const double rate = ops / (best * 1e-3);
   std::printf("{\"kernel\": \"%s\", \"waves_per_simd\": %d, \"ms\": %.4f, "
@@ -99,6 +108,9 @@ int main() {
   if (run<1>("add_vgpr_only", cus, 8, out, in)) return 1;
   for (int w : {1, 2, 4, 8})
     if (run<2>("dp_cell_vgpr_only", cus, w, out, in)) return 1;
+  if (run<3>("fma_vgpr_only", cus, 8, out, in)) return 1;
+  for (int w : {1, 2, 4, 8})
+    if (run<4>("code_cell_vgpr_only", cus, w, out, in)) return 1;
   CHK(hipFree(out));
   CHK(hipFree(in));
   return 0;

@@ -214,8 +214,8 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
   L.corner = up[T - 1];
   const int tau_out = g - G.out_delay;
   const bool do_out = OUTK >= 0 && tau_out >= 0 && tau_out < G.ntiles;
-  if constexpr (Val<V>::N == 2) {
-    // Packed binary16: anti-diagonal order.  gfx950 needs a wait state
+  if constexpr (Val<V>::kAntiDiagonal) {
+    // Anti-diagonal order (packed binary16): gfx950 needs a wait state
     // between dependent packed instructions; cells (k, t) and (k+1, t-1)
     // are independent, so this order puts independent work between them.
     V D[R][T];
@@ -228,8 +228,7 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
         const V u = k == 0 ? up[t] : D[k - 1][t];
         const V lf = t == 0 ? L.dl[k] : D[k][t - 1];
         const V dg = t == 0 ? (k == 0 ? upleft : L.dl[k - 1]) : (k == 0 ? up[t - 1] : D[k - 1][t - 1]);
-        const V c = Val<V>::template cost<KIND>(L.qv[k], rv[t], L.tau);
-        D[k][t] = Val<V>::add(Val<V>::min3(u, lf, dg), c);
+        D[k][t] = Val<V>::template cell<KIND>(L.qv[k], rv[t], u, lf, dg, L.tau);
       }
     }
     if constexpr (OUTK >= 0) {

@@ -30,6 +30,7 @@ template <>
 struct Val<float> {
   using In = float;                            // element type in HBM
   static constexpr int N = 1;                  // queries per value
+  static constexpr bool kAntiDiagonal = false; // cell order in a step's block
   __device__ static float inf() { return inf_f32(); }
   __device__ static float zero() { return 0.0f; }
   __device__ static float query(float a, float) { return a; }
@@ -51,6 +52,7 @@ template <>
 struct Val<f16x2> {
   using In = float;
   static constexpr int N = 2;
+  static constexpr bool kAntiDiagonal = true;
   __device__ static f16x2 inf() {
     const _Float16 h = (_Float16)__builtin_huge_valf();
     return f16x2{h, h};
@@ -86,6 +88,11 @@ struct Val<f16x2> {
     return __builtin_bit_cast(f16x2, m);
   }
   __device__ static f16x2 add(f16x2 a, f16x2 b) { return a + b; }          // v_pk_add_f16
+  template <int KIND>
+  __device__ static f16x2 cell(f16x2 q, f16x2 r, f16x2 up, f16x2 left, f16x2 diag, float tau) {
+    const f16x2 c = cost<KIND>(q, r, tau);
+    return add(min3(up, left, diag), c);
+  }
   __device__ static f16x2 shr1(f16x2 lane0, f16x2 v) {
     return __builtin_bit_cast(
         f16x2, wave_shr1(__builtin_bit_cast(float, lane0), __builtin_bit_cast(float, v)));
@@ -108,6 +115,7 @@ template <>
 struct Val<Code8> {
   using In = uint8_t;
   static constexpr int N = 1;
+  static constexpr bool kAntiDiagonal = false;  // measured: row order is as fast
   __device__ static Code8 inf() { return Code8{inf_f32()}; }
   __device__ static Code8 zero() { return Code8{0.0f}; }
   __device__ static Code8 query(uint8_t a, uint8_t) { return Code8{(float)a}; }
