@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd16_kernel(const FwdParams p
   fwd_query<R, T, W, KS, XL, KIND, false, f16x2>(p, b, query_offset(p, b), row, s_mem);
 }
 
-// uint8-code form (integer DP on quantised values): one workgroup per query;
+// uint8-code form (binary32 DP of quantised values): one workgroup per query;
 // queries and reference hold one code byte per element.
 template <int R, int T, int W, int KS, int XL>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_u8_kernel(const FwdParams p) {
