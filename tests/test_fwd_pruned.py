@@ -102,3 +102,17 @@ def test_pruned_full_size_sampled():
         print(f"pruned full size variant {v}", flush=True)
         c, e = _gpu_pruned(w, 2.0, v)
         assert_bit_exact(c[idx], e[idx], want_c, want_e, f"pruned 512x2000 variant {v}")
+
+
+def test_pruned_uneven_batch_persistent_subset():
+    """4,096 queries of 250..4,000 samples against 200,000 in one persistent
+    launch with tau = 2; a seeded subset (shortest and longest included)
+    checked against the oracle."""
+    import paper_2403_06931_amd as P
+    w = workloads.make_config(3)
+    print("pruned uneven batch, persistent", flush=True)
+    c, e = _gpu_pruned(w, 2.0, flags=P.SDTW_F_PERSISTENT)
+    idx = workloads.subset_indices(w, 8, seed=15, include_extremes=True)
+    sub = w.subset(idx)
+    want_c, want_e = oracle.sdtw_pruned_f32(sub.queries, sub.lens, sub.reference, 2.0)
+    assert_bit_exact(c[idx], e[idx], want_c, want_e, "pruned uneven batch subset")

@@ -94,3 +94,16 @@ def test_u8_full_size_sampled():
         print(f"u8 full size variant {v}", flush=True)
         c, e, book = _gpu_u8(w, v)
         _check(sub, (c[idx], e[idx], book), f"u8 512x2000 variant {v}", want=want)
+
+
+def test_u8_uneven_batch_subset():
+    """4,096 queries of 250..4,000 samples against 200,000 (offset table
+    path); a seeded subset with the shortest and longest against the oracle,
+    which codes the subset with the codebook of the whole reference."""
+    w = workloads.make_config(3)
+    idx = workloads.subset_indices(w, 8, seed=16, include_extremes=True)
+    sub = w.subset(idx)
+    want = Q.sdtw_u8(sub.queries, sub.lens, w.reference)
+    print("u8 uneven batch", flush=True)
+    c, e, book = _gpu_u8(w)
+    _check(sub, (c[idx], e[idx], book), "u8 uneven batch subset", want=want)
