@@ -71,9 +71,11 @@ template <int R, int T, int W, int KS, int XL>
 struct FwdShape {
   static_assert(KS % 2 == 0, "the step loop is unrolled by two");
   static constexpr int KSTEP = KS;
-  // lane -> lane exchange: XL = 1 through LDS slots (lane l+1 lags lane l by
-  // two steps), XL = 0 through a DPP wave_shr:1 move (one step)
-  static constexpr int LL = XL ? 2 : 1;
+  // lane -> lane exchange: XL = 1 through LDS slots, XL = 0 through a DPP
+  // wave_shr:1 move; either way lane l+1 lags lane l by one step (a slot is
+  // read inside the step that uses it, after the neighbour's write at the
+  // end of the previous step)
+  static constexpr int LL = 1;
   // Extra lag of wave w+1 behind wave w.  Data a wave hands over at step p is
   // read (one step early, by the prefetch) at step p + KS + 1, always in a
   // later barrier interval.
@@ -208,8 +210,18 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
                                          const V (&top)[T], int g, V* s_hand, V* s_slot) {
   using S = FwdShape<R, T, W, KS, XL>;
   V up[T];
+  if constexpr (XL) {
+    // lane l-1's slot, written at the end of step g-1 (lane 0: this wave's
+    // handoff ring); the read's latency is covered by the block's
+    // subtractions and products, which do not depend on it
+    const V* hin = s_hand + G.wave * S::SH * T + ((g - G.lane0_delay) & (S::SH - 1)) * T;
+    const V* tin = G.lane != 0 ? s_slot + (G.wave * kWave + G.lane - 1) * T : hin;
 #pragma unroll
-  for (int t = 0; t < T; ++t) up[t] = XL ? top[t] : Val<V>::shr1(top[t], L.bot[t]);
+    for (int t = 0; t < T; ++t) up[t] = tin[t];
+  } else {
+#pragma unroll
+    for (int t = 0; t < T; ++t) up[t] = Val<V>::shr1(top[t], L.bot[t]);
+  }
   V upleft = L.corner;                          // D(row-1, first col - 1)
   L.corner = up[T - 1];
   const int tau_out = g - G.out_delay;
@@ -276,11 +288,15 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
   for (int t = 0; t < T; ++t) L.bot[t] = up[t];
 
   if constexpr (XL) {
-    // the bottom row feeds lane l+1 (its slot is read during the next step,
-    // before this lane overwrites it at the end of that step)
+    // the bottom row feeds lane l+1 (its slot is read at the start of the
+    // next step, before this lane overwrites it at the end of that step).
+    // LDS operations of one wavefront complete in order; the compiler must
+    // not move the next step's slot read (another lane's slot, so no alias
+    // in one thread's view) above this store.
     V* sout = s_slot + (G.wave * kWave + G.lane) * T;
 #pragma unroll
     for (int t = 0; t < T; ++t) sout[t] = L.bot[t];
+    asm volatile("" ::: "memory");
   }
 
   // lane 63 hands its bottom row to the next wave
@@ -306,21 +322,19 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
   }
 }
 
-// LDS inputs of step g: this lane's reference tile and its top boundary
-// (lane 0: this wave's handoff ring; with XL the others read lane l-1's
-// slot, written at the end of step g-2; without, every lane reads the ring
-// and fwd_step shifts the bottom rows instead).
+// LDS inputs of step g, read one step ahead: this lane's reference tile and,
+// without XL, the handoff ring's top boundary (fwd_step shifts the bottom
+// rows to the other lanes); with XL, fwd_step reads the top boundary itself.
 template <int R, int T, int W, int KS, int XL, typename V>
 __device__ __forceinline__ void step_inputs(V (&rv)[T], V (&top)[T], int g, const PassGeom& G,
                                             const V* s_ref, const V* s_hand, const V* s_slot) {
   using S = FwdShape<R, T, W, KS, XL>;
   const V* rin = s_ref + ((g - G.my_delay) & (S::SR - 1)) * T;
   const V* hin = s_hand + G.wave * S::SH * T + ((g - G.lane0_delay) & (S::SH - 1)) * T;
-  const V* tin = (XL && G.lane != 0) ? s_slot + (G.wave * kWave + G.lane - 1) * T : hin;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     rv[t] = rin[t];
-    top[t] = tin[t];
+    if constexpr (!XL) top[t] = hin[t];
   }
 }
 
