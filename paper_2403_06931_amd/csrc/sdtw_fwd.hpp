@@ -77,8 +77,8 @@ struct FwdShape {
   // end of the previous step)
   static constexpr int LL = 1;
   // Extra lag of wave w+1 behind wave w.  Data a wave hands over at step p is
-  // read (one step early, by the prefetch) at step p + KS + 1, always in a
-  // later barrier interval.
+  // used at step p + KS + 1 (read inside that step with XL, by the prefetch
+  // one step earlier without), always in a later barrier interval.
   static constexpr int LAG = KS;
   static constexpr int SH = 4 * KS;                           // handoff rings, tiles
   // reference tiles in flight: the oldest lane's tile up to the tiles staged
@@ -372,8 +372,9 @@ __device__ __forceinline__ void out_copy(const PassGeom& G, int it) {
   }
 }
 
-// All barrier intervals of one pass.  The LDS inputs of step g+1 are read
-// while step g computes (two register sets, the step loop unrolled by two).
+// All barrier intervals of one pass.  The reference tile of step g+1 (and,
+// without XL, its handoff input) is read while step g computes (two register
+// sets, the step loop unrolled by two).
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK, typename V>
 __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>& L,
                                          const PassGeom& G, const V* prev_row, V* s_ref,
