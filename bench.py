@@ -98,20 +98,6 @@ def measured_traffic(kernel_tag):
         return None
 
 
-def valu_issue_probe():
-    """Build (into _build/) and run bench_valu_issue.hip; return its records."""
-    import subprocess
-    src = os.path.join(ROOT, "bench_valu_issue.hip")
-    exe = os.path.join(ROOT, "_build", "bench_valu_issue")
-    if not os.path.exists(exe) or os.path.getmtime(exe) < os.path.getmtime(src):
-        os.makedirs(os.path.dirname(exe), exist_ok=True)
-        subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-ffp-contract=off",
-                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", src, "-o", exe],
-                       check=True, capture_output=True)
-    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
-    return [json.loads(line) for line in out.splitlines() if line.startswith("{")]
-
-
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -467,8 +453,6 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and fwd+bwd legs")
-    ap.add_argument("--valu-issue-probe", action="store_true",
-                    help="only measure the FP32 VALU issue rate (bench_valu_issue.hip) and exit")
     ap.add_argument("--u8-only", action="store_true",
                     help="only time the uint8-code forward (sdtw_forward_u8) and exit")
     ap.add_argument("--znorm-only", action="store_true",
@@ -482,11 +466,6 @@ def main():
                                    "over queries without communication, so run --gpus 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-
-    if args.valu_issue_probe:
-        for rec in valu_issue_probe():
-            print(json.dumps(rec), flush=True)
-        return
 
     import numpy as np
     import torch

@@ -302,7 +302,7 @@ SDTW_API int sdtw_align(const float *queries, const int32_t *h_query_lens,
 
 /*
  * Batch z-normalisation, the step that prepares queries and reference
- * (paper: Section 3, "Normalizer implementation", standardisation equation):
+ * (paper: Section 5.1, "Normalizer implementation", standardisation equation):
  * every series of a packed batch becomes
  *
  *     z_k = (x_k - mean) / S,   mean = (1/n) sum x_k,

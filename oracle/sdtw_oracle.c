@@ -397,8 +397,10 @@ int oracle_sdtw_last_row_f32(const float *q, int32_t n, const float *ref,
 
 /*
  * Global (corner-to-corner) DTW in FP32, the textbook alignment of Section 2:
- * D(0,0) = 0, D(0,j>0) = D(i>0,0) = +inf, result D(N,M).  Used only as an
- * upper bound on the subsequence cost in the tests.
+ * D(0,0) = 0, D(0,j>0) = D(i>0,0) = +inf, result D(N,M).  The tests use it
+ * as an upper bound on the subsequence cost; it is pinned on its own by a
+ * brute-force enumeration of every corner-to-corner warp path (bit for bit
+ * in binary32) and by a hand-worked table of the 3 x 6 example.
  */
 int oracle_dtw_f32(const float *q, int32_t n, const float *ref,
                    int64_t ref_len, int kind, float *out)

@@ -3,7 +3,7 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
 leg may import this module; the HIP library shares no code with it.
 
-The paper's normaliser (Section 3, "Normalizer implementation", and its
+The paper's normaliser (Section 5.1, "Normalizer implementation", and its
 standardisation equation) rescales every series of a packed batch to mean 0
 and standard deviation 1: z = (x - mean) / S.  Readings where the paper is
 silent or loose:

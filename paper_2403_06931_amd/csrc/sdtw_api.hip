@@ -137,8 +137,9 @@ double variant_cost(const Variant& v, const int32_t* h_lens, int32_t batch, int6
                     int cus) {
   const int64_t rows = 64LL * v.R * v.W;
   const int64_t ntiles = (ref_len + v.T - 1) / v.T;
-  const int64_t lane_lag = v.XL ? 2 : 1;
-  const int64_t skew = lane_lag * (64LL * v.W - 1) + (v.W - 1) * v.KS;
+  // pipeline fill: each lane lags its neighbour by one step (both exchange
+  // forms), each wavefront the previous one by KS steps more
+  const int64_t skew = (64LL * v.W - 1) + (v.W - 1) * v.KS;
   double cells = 0;
   for (int32_t b = 0; b < batch; ++b) {
     const int64_t passes = (h_lens[b] + rows - 1) / rows;

@@ -55,7 +55,9 @@ __device__ __forceinline__ float vgpr_copy(float x) {
   return v;
 }
 
-// Exact three-way minimum (one v_min3_f32).  Inputs are never NaN here.
+// Exact three-way minimum (one v_min3_f32).  Inputs are never NaN here: DP
+// values start at 0 or +inf and every LDS slot a lane reads before its
+// first tile is initialised (+inf boundaries, a zeroed reference ring).
 __device__ __forceinline__ float min3(float a, float b, float c) {
   return __builtin_fminf(__builtin_fminf(a, b), c);
 }

@@ -8,14 +8,15 @@
 //     current column in registers;
 //   * the reference is streamed in tiles of T columns: at global step g a lane
 //     whose team position is L = 64*w + l computes the R x T block of tile
-//     tau = g - 2L - w*LAG;
+//     tau = g - L - w*LAG;
 //   * the DP values of a lane's bottom row for the T columns of a tile feed the
-//     next lane through a per-lane LDS slot (the paper's lane shuffle, Section
-//     5.2).  Lanes lag their neighbour by two steps, so the slot written at the
-//     end of step g is read, one step ahead, during step g+1 and the LDS
-//     latency hides behind a step of arithmetic.  (A DPP lane shift is the
-//     obvious alternative; on gfx950 its DPP moves keep the SIMD from
-//     dual-issuing and measured about 20 % slower.)
+//     next lane (the paper's lane shuffle, Section 5.2), either through a
+//     per-lane LDS slot or by a DPP wave_shr:1 lane shift (chosen per tile
+//     variant).  Lanes lag their neighbour by one step: the value written at
+//     the end of step g is read inside step g+1, its LDS latency hidden
+//     behind the step's subtractions and products, which do not depend on
+//     it.  (On gfx950 DPP moves keep the SIMD from dual-issuing; the LDS form
+//     is faster for the large-R tiles, the DPP form for 2-row tiles.)
 //   * lane 63 of wave w hands its bottom row to lane 0 of wave w+1 through an
 //     LDS ring (the paper's shared-memory handoff between consecutive
 //     wavefronts); lane 0 reads it with the same load that reads the other
@@ -35,9 +36,11 @@
 // Section 5.2 reduces that row to its minimum).  Row N never goes to HBM.
 //
 // Lanes that are still before their first tile (tau < 0) hold +inf in every
-// register and only ever see +inf from their neighbours, so they stay +inf
-// and need no masking; columns past the end of the reference read zeros and
-// produce values nobody reads.
+// register and only ever see +inf from their neighbours; the reference slots
+// they read are zero-filled at the start of each pass (or hold an earlier
+// tile), so their cells are +inf + a finite cost = +inf and need no masking.
+// Columns past the end of the reference read zeros and produce values nobody
+// reads.
 #pragma once
 
 #include "sdtw_argmin.hpp"
@@ -506,9 +509,12 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
     const V* prev_row = pass > 0 ? reinterpret_cast<const V*>(row) : nullptr;
 
     // +inf handoff rings and lane slots (a lane before its first tile must
-    // see +inf), then the first two intervals of reference and top boundary.
+    // see +inf), a zeroed reference ring (so that those lanes compute on
+    // finite values, never on whatever the LDS held), then the first two
+    // intervals of reference and top boundary.
     for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
     for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
+    for (int e = tid; e < S::SR * T; e += S::THREADS) s_ref[e] = Val<V>::zero();
     __syncthreads();
     {
       Stager<R, T, W, KS, XL, V> st0, st1;

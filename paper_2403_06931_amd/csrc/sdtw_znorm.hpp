@@ -1,5 +1,5 @@
 // sdtw_znorm.hpp -- batch z-normalisation, the step before the DP (the
-// paper's normaliser, Section 3 "Normalizer implementation", standardisation
+// paper's normaliser, Section 5.1 "Normalizer implementation", standardisation
 // equation): every series of a packed batch becomes z = (x - mean) / S with S
 // the population standard deviation.  Included by the API translation unit
 // only.

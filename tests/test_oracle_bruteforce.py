@@ -196,3 +196,54 @@ def test_walk_back_tie_break(kind):
             want.append((i, j))
         pi, pj = oracle.path_f32(q, r, kind)
         assert list(zip(pi.tolist(), pj.tolist())) == want, (q, r)
+
+
+def brute_force_dtw_f32(q, r, kind):
+    """Global (corner-to-corner) DTW of Section 2 by enumeration: every warp
+    path from cell (1, 1) to cell (N, M) with steps down, right and diagonal,
+    its FP32 costs folded left to right from (1, 1); the minimum fold."""
+    n, m = len(q), len(r)
+    c = [[_c32(q[i], r[j], kind) for j in range(m)] for i in range(n)]
+    best = [np.float32(np.inf)]
+
+    def walk(i, j, acc):
+        if i == n - 1 and j == m - 1:
+            if acc < best[0]:
+                best[0] = acc
+            return
+        for di, dj in ((1, 0), (0, 1), (1, 1)):
+            ni, nj = i + di, j + dj
+            if ni < n and nj < m:
+                walk(ni, nj, np.float32(acc + c[ni][nj]))
+
+    walk(0, 0, c[0][0])
+    return best[0]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_global_dtw_equals_brute_force_bit_exact(kind):
+    """oracle.dtw_f32 (the corner-to-corner DTW the subsequence cost is bounded
+    by) against the enumeration above, bit for bit, including small-integer
+    inputs with many ties and single-row / single-column shapes."""
+    for q, r in _cases():
+        want = brute_force_dtw_f32(q, r, kind)
+        got = oracle.dtw_f32(q, r, kind)
+        assert np.float32(got).tobytes() == want.tobytes(), (q, r, got, want)
+        # the free start can only lower the cost, and the corner path is one
+        # of the subsequence paths
+        cost, _ = oracle.sdtw_f32(q, [q.size], r, kind)
+        assert cost[0] <= got
+
+
+def test_global_dtw_hand_worked_example():
+    """Every entry G(i, j) of the hand-worked global DTW table is the DTW of
+    the prefixes q[:i] and r[:j]."""
+    g = _read_golden("hand_sdtw_3x6.txt")
+    q = np.array(g["q"], np.float32)
+    r = np.array(g["r"], np.float32)
+    for kind, name in ((0, "squared"), (1, "absolute")):
+        rows = np.array(g[f"{name}.dtw_rows"], np.float32).reshape(3, 6)
+        for i in range(1, 4):
+            for j in range(1, 7):
+                assert oracle.dtw_f32(q[:i], r[:j], kind) == rows[i - 1, j - 1], (name, i, j)
+        assert oracle.dtw_f32(q, r, kind) == g[f"{name}.dtw"][0]
