@@ -9,11 +9,16 @@ call over the whole batch (DP fill, last-row minimum and end position), with
 every input already resident in device memory.
 
 Prints ONE JSON line.  Beside the headline value it reports:
-  roofline      the dominant kernel against the FP32 VALU roofline: gfx950
-                issues up to two VGPR-operand FP32 VALU instructions per SIMD
-                per quad-cycle, i.e. 256 CUs x 128 lanes x 2.4 GHz, divided by
-                the 4 VALU instructions of a DP cell;
-  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
+  roofline      the dominant kernel against the chip's FP32 vector peak,
+                157.3 TFLOP/s (256 CUs x 2.4 GHz; an FMA counted as two
+                flops), with a DP cell counted as 5 flops (subtraction,
+                product, two comparisons of the three-way minimum, sum); and
+                against the issue ceiling of its own instructions: 4 VALU
+                instructions per cell, two per SIMD per quad-cycle at most
+                (78.6 T lane-instructions/s), both also at the shader clock
+                measured during a sustained run;
+  cpu_baseline  the CPU oracle timed on the same workload (all 512 queries)
+                on the host's cores, checked bit for bit against the GPU;
   batched       the persistent uneven-length form (4,096 queries of
                 250..4,000 samples vs 200,000) and the same batch run as a
                 loop of plain launches over 16 length buckets;
@@ -56,6 +61,10 @@ PAPER_GCUPS = PAPER_CELLS / (PAPER_MS * 1e6)
 PEAK_CUS = 256
 PEAK_GHZ = 2.4
 LANES_PER_CU_CLK = 128      # 4 SIMDs x 16 lanes x 2 (VALU dual issue)
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (FMA = 2 flops)
+# flops of one DP cell: subtraction, product (squared cost only), the two
+# comparisons of the three-way minimum, sum
+FLOPS_PER_CELL = {"squared": 5, "absolute": 4}
 
 
 def valu_peak_gcups(ops_per_cell, cus=PEAK_CUS, ghz=PEAK_GHZ, lanes=LANES_PER_CU_CLK):
@@ -98,6 +107,92 @@ def measured_traffic(kernel_tag):
         return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def sample_sclk(run, launches, torch):
+    """Median graphics clock (GHz) reported by amd-smi while `launches` calls of
+    `run` keep the GPU busy; None where the clock cannot be read."""
+    import threading
+    try:
+        import amdsmi
+    except ImportError:
+        return None
+    samples, stop, state = [], threading.Event(), {}
+
+    def poll():
+        try:
+            amdsmi.amdsmi_init()
+            handles = amdsmi.amdsmi_get_processor_handles()
+            bus = getattr(torch.cuda.get_device_properties(0), "pci_bus_id", None)
+            pick = handles[0] if len(handles) == 1 else None
+            for h in handles:
+                if bus is not None and pick is None:
+                    bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)
+                    if int(bdf.split(":")[1], 16) == int(bus):
+                        pick = h
+            if pick is None:
+                return
+            state["ok"] = True
+            while not stop.is_set():
+                samples.append(amdsmi.amdsmi_get_clock_info(
+                    pick, amdsmi.AmdSmiClkType.GFX)["clk"])
+                time.sleep(0.005)
+        except Exception as exc:                  # noqa: BLE001 - reported as unavailable
+            state["error"] = repr(exc)
+        finally:
+            try:
+                amdsmi.amdsmi_shut_down()
+            except Exception:                     # noqa: BLE001
+                pass
+
+    t = threading.Thread(target=poll, daemon=True)
+    for _ in range(launches):
+        run()
+    t.start()
+    torch.cuda.synchronize()
+    stop.set()
+    t.join(5)
+    vals = sorted(v for v in samples if isinstance(v, (int, float)) and v > 0)
+    if not vals:
+        return None
+    return {"ghz": vals[len(vals) // 2] / 1000.0, "samples": len(vals),
+            "min_ghz": vals[0] / 1000.0, "max_ghz": vals[-1] / 1000.0}
+
+
+def oracle_subset(w, idx, kind, gpu_cost, gpu_end, cores):
+    """The oracle on queries idx of workload w: GCUPS on the host cores, the
+    full workload's time extrapolated from it, and bit-exact agreement with
+    the GPU's results for those queries."""
+    import numpy as np
+
+    import oracle
+    sub = w.subset(idx)
+    t0 = time.perf_counter()
+    c, e = oracle.sdtw_f32(sub.queries, sub.lens, sub.reference, kind, nthreads=cores)
+    dt = time.perf_counter() - t0
+    gcups = sub.cells / dt / 1e9
+    return {"gcups": gcups, "cores": int(cores), "queries": int(len(idx)),
+            "wall_s": dt, "extrapolated_full_s": w.cells / (gcups * 1e9),
+            "bit_exact_vs_gpu": bool(np.array_equal(c.view(np.uint32),
+                                                    gpu_cost[idx].view(np.uint32))
+                                     and np.array_equal(e, gpu_end[idx]))}
+
+
+def host_cores():
+    import oracle
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(cores, oracle.max_threads()))
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -115,25 +210,18 @@ def time_steps(fn, steps, warmup, torch):
 
 
 def cpu_baseline(w, gpu_cost, gpu_end):
+    """The FP32 oracle on every query of the headline workload, OpenMP over
+    queries on the host's cores."""
     import numpy as np
-
-    import oracle
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(cores, oracle.max_threads()))
-    count = min(w.batch, 8 * cores)
-    idx = np.arange(count)
-    sub = w.subset(idx)
-    t0 = time.perf_counter()
-    c, e = oracle.sdtw_f32(sub.queries, sub.lens, sub.reference, 0, nthreads=cores)
-    dt = time.perf_counter() - t0
-    parity = bool(np.array_equal(c.view(np.uint32), gpu_cost[idx].view(np.uint32)) and
-                  np.array_equal(e, gpu_end[idx]))
-    return {"value": sub.cells / dt / 1e9, "unit": "GCUPS", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {count} of 512 queries (2,000 x 100,000 cells each), "
-                      f"{dt:.1f} s wall", "bit_exact_vs_gpu": parity}
+    cores = host_cores()
+    rec = oracle_subset(w, np.arange(w.batch), 0, gpu_cost, gpu_end, cores)
+    return {"value": rec["gcups"], "unit": "GCUPS", "cores": rec["cores"], "kind": "oracle",
+            "sample": f"all {w.batch} queries (2,000 x 100,000 cells each), "
+                      f"{rec['wall_s']:.1f} s wall", "cpu_model": cpu_model(),
+            "bit_exact_vs_gpu": rec["bit_exact_vs_gpu"]}
 
 
-def batched_leg(P, torch, steps, warmup):
+def batched_leg(P, torch, steps, warmup, oracle_legs=True):
     import numpy as np
 
     import workloads
@@ -143,20 +231,17 @@ def batched_leg(P, torch, steps, warmup):
     l = torch.from_numpy(w.lens).to(dev)
     r = torch.from_numpy(w.reference).to(dev)
     flags = P.SDTW_F_PERSISTENT
-    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags), dev)
-    cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
-    end = torch.empty(w.batch, dtype=torch.int64, device=dev)
     rec = {}
     # persistent candidates: at most four wavefronts per query (wider teams
     # waste most of their lanes on the short queries of this batch)
     cands = [v for v in range(P.sdtw_variant_count()) if P.sdtw_variant_info(v)[2] <= 4]
     variant = P.autotune.tune(q, w.lens, l, r, 0, flags, candidates=cands, reps=1, record=rec)
-
-    def persistent():
-        P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, flags=flags, variant=variant,
-                       workspace_buf=ws)
-    wall_ms, ev_ms = time_steps(persistent, steps, warmup, torch)
-    pc = cost.cpu().numpy().copy()
+    # the timed step is the captured launch sequence (order + work-counter
+    # reset, persistent kernel), replayed
+    g = P.ForwardGraph(q, w.lens, l, r, 0, flags=flags, variant=variant)
+    wall_ms, ev_ms = time_steps(g.replay, steps, warmup, torch)
+    pc = g.cost.cpu().numpy().copy()
+    pe = g.end_pos.cpu().numpy().copy()
 
     # baseline: plain launches over 16 equal-width length buckets
     edges = np.linspace(w.lens.min(), w.lens.max() + 1, 17)
@@ -179,15 +264,24 @@ def batched_leg(P, torch, steps, warmup):
     bwall, bev = time_steps(bucketed, steps, warmup, torch)
     same = all(np.array_equal(cb.cpu().numpy().view(np.uint32), pc[idx].view(np.uint32))
                for idx, _, _, _, _, cb, _ in buckets)
-    del ws
-    return {"workload": w.name, "cells": w.cells, "variant": P.sdtw_variant_info(variant),
-            "tuned_over": len(rec.get("times_ms", {})),
-            "gcups": w.cells / (ev_ms * 1e6), "ms_per_step": ev_ms,
-            "bucketed_loop_gcups": w.cells / (bev * 1e6), "bucketed_loop_ms": bev,
-            "bit_identical_to_bucketed": bool(same)}
+    del g, buckets
+    out = {"workload": w.name, "digest": workloads.digest(w), "cells": w.cells,
+           "variant": P.sdtw_variant_info(variant), "tuned_over": len(rec.get("times_ms", {})),
+           "timed": "ForwardGraph.replay() (hipGraph of the persistent launch)",
+           "gcups": w.cells / (ev_ms * 1e6), "ms_per_step": ev_ms,
+           "gsps": float(w.lens.sum()) / (ev_ms * 1e6),
+           "bucketed_loop_gcups": w.cells / (bev * 1e6), "bucketed_loop_ms": bev,
+           "bit_identical_to_bucketed": bool(same)}
+    if oracle_legs:
+        # 64 seeded queries, two of them the shortest and the longest
+        extremes = {int(np.argmin(w.lens)), int(np.argmax(w.lens))}
+        rest = [int(b) for b in workloads.subset_indices(w, 70, seed=31) if b not in extremes]
+        idx = np.array(sorted(extremes | set(rest[:64 - len(extremes)])), np.int64)
+        out["oracle"] = oracle_subset(w, idx, 0, pc, pe, host_cores())
+    return out
 
 
-def fwd_bwd_leg(P, torch, steps, warmup):
+def fwd_bwd_leg(P, torch, steps, warmup, oracle_legs=True):
     import numpy as np
 
     import workloads
@@ -198,7 +292,6 @@ def fwd_bwd_leg(P, torch, steps, warmup):
     r = torch.from_numpy(w.reference).to(dev)
     K = 1024
     flags = P.SDTW_F_CHECKPOINT
-    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags), dev)
     wsb = P.workspace(P.sdtw_backward_workspace_bytes(w.lens, w.ref_len, K), dev)
     ckpt = torch.empty(P.sdtw_checkpoint_floats(w.lens, w.ref_len, K), dtype=torch.float32,
                        device=dev)
@@ -212,6 +305,7 @@ def fwd_bwd_leg(P, torch, steps, warmup):
     from paper_2403_06931_amd import autotune as A
     rec = {}
     var = A.tune(q, w.lens, l, r, 0, flags, reps=2, record=rec, ckpt=ckpt, ckpt_every=K)
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, flags, var), dev)
 
     def fwd():
         P.sdtw_forward(q, w.lens, l, r, 0, cost=cost, end_pos=end, ckpt=ckpt, ckpt_every=K,
@@ -241,36 +335,65 @@ def fwd_bwd_leg(P, torch, steps, warmup):
     def align():
         P.sdtw_align(q, w.lens, l, r, 0, cost, end, ckpt, K, workspace_buf=wsa)
     _, a_ms = time_steps(align, steps, warmup, torch)
-    return {"workload": w.name, "cells": w.cells, "ckpt_every": K,
-            "gcups": w.cells / (fb_ms * 1e6), "ms_per_step": fb_ms,
-            "fwd_ckpt_ms": f_ms, "bwd_ms": b_ms, "plain_fwd_ms": p_ms,
-            "plain_fwd_gcups": w.cells / (p_ms * 1e6), "align_ms": a_ms,
-            "variant": P.sdtw_variant_info(var), "tuned_over": len(rec.get("times_ms", {}))}
+    out = {"workload": w.name, "digest": workloads.digest(w), "cells": w.cells,
+           "ckpt_every": K, "gcups": w.cells / (fb_ms * 1e6), "ms_per_step": fb_ms,
+           "fwd_ckpt_ms": f_ms, "bwd_ms": b_ms, "plain_fwd_ms": p_ms,
+           "plain_fwd_gcups": w.cells / (p_ms * 1e6), "align_ms": a_ms,
+           "variant": P.sdtw_variant_info(var), "tuned_over": len(rec.get("times_ms", {}))}
+    if oracle_legs:
+        import oracle
+        both()
+        torch.cuda.synchronize()
+        cores = host_cores()
+        t0 = time.perf_counter()
+        oc, oe, _, ogq, ogr = oracle.sdtw_grad_f32(w.queries, w.lens, w.reference,
+                                                   np.ones(w.batch, np.float32), 0,
+                                                   nthreads=cores)
+        dt = time.perf_counter() - t0
+        same = (np.array_equal(oc.view(np.uint32), cost.cpu().numpy().view(np.uint32))
+                and np.array_equal(oe, end.cpu().numpy())
+                and np.array_equal(ogq.view(np.uint32), gq.cpu().numpy().view(np.uint32))
+                and np.array_equal(ogr.view(np.uint32), gr.cpu().numpy().view(np.uint32)))
+        out["oracle"] = {"what": "full-matrix forward and walk-back gradient, all 256 queries",
+                         "gcups": w.cells / dt / 1e9, "cores": int(cores), "wall_s": dt,
+                         "bit_exact_vs_gpu": bool(same)}
+    return out
 
 
 HBM_PEAK_GBS = 8000.0
 
 
-def long_ref_leg(P, torch, variant, steps, warmup):
+def long_ref_leg(P, torch, variant, steps, warmup, oracle_legs=True):
     """512 x 2,000 vs 2,000,000, both cost kinds, in the headline's tile."""
+    import numpy as np
+
     import workloads
     w = workloads.make_config(2)
     dev = torch.device("cuda:0")
     q = torch.from_numpy(w.queries).to(dev)
     l = torch.from_numpy(w.lens).to(dev)
     r = torch.from_numpy(w.reference).to(dev)
-    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0, variant), dev)
     cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
     end = torch.empty(w.batch, dtype=torch.int64, device=dev)
-    out = {"workload": w.name, "cells": w.cells, "variant": P.sdtw_variant_info(variant)}
+    out = {"workload": w.name, "digest": workloads.digest(w), "cells": w.cells,
+           "variant": P.sdtw_variant_info(variant),
+           "workspace_bytes": int(ws.numel())}
     for kind, name, ops in ((0, "squared", 4), (1, "absolute", 3)):
         def step(kind=kind):
             P.sdtw_forward(q, w.lens, l, r, kind, cost=cost, end_pos=end, variant=variant,
                            workspace_buf=ws)
         wall_ms, ev_ms = time_steps(step, steps, warmup, torch)
         peak = valu_peak_gcups(ops)
+        gcups = w.cells / (ev_ms * 1e6)
         out[name] = {"ms_per_step": wall_ms, "gcups": w.cells / (wall_ms * 1e6),
-                     "roofline_frac": w.cells / (ev_ms * 1e6) / peak, "peak_gcups": peak}
+                     "issue_frac": gcups / peak, "peak_gcups": peak,
+                     "flop_frac": gcups * FLOPS_PER_CELL[name] / 1e3 / PEAK_FP32_TFLOPS}
+        if oracle_legs:
+            idx = np.sort(np.random.default_rng(workloads.BASE_SEED + 2 + kind)
+                          .choice(w.batch, 16, replace=False))
+            out[name]["oracle"] = oracle_subset(w, idx, kind, cost.cpu().numpy(),
+                                                end.cpu().numpy(), host_cores())
     return out
 
 
@@ -321,7 +444,8 @@ def pruned_leg(P, torch, exact_cost, exact_end, steps, warmup):
     q = torch.from_numpy(w.queries).to(dev)
     l = torch.from_numpy(w.lens).to(dev)
     r = torch.from_numpy(w.reference).to(dev)
-    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
+    ws = P.workspace(max(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0, v)
+                         for v in range(P.sdtw_variant_count())), dev)
     cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
     end = torch.empty(w.batch, dtype=torch.int64, device=dev)
     tau0 = 2.0
@@ -488,7 +612,6 @@ def main():
     q = torch.from_numpy(w.queries).to(dev)
     l = torch.from_numpy(w.lens).to(dev)
     r = torch.from_numpy(w.reference).to(dev)
-    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0), dev)
     cost = torch.empty(w.batch, dtype=torch.float32, device=dev)
     end = torch.empty(w.batch, dtype=torch.int64, device=dev)
     if args.variant >= 0:
@@ -497,6 +620,7 @@ def main():
         variant = P.sdtw_default_variant(w.lens, w.ref_len, 0)
     else:
         variant = P.autotune.tune(q, w.lens, l, r, 0, 0, reps=3)
+    ws = P.workspace(P.sdtw_forward_workspace_bytes(w.lens, w.ref_len, 0, variant), dev)
 
     def step():
         P.sdtw_forward(q, w.lens, l, r, P.SDTW_COST_SQUARED, cost=cost, end_pos=end,
@@ -505,11 +629,16 @@ def main():
     wall_ms, ev_ms = time_steps(step, args.steps, args.warmup, torch)
     cells = w.cells
     value = cells / (wall_ms * 1e6)
-    achieved = cells / (ev_ms * 1e6)          # one kernel launch per step at this batch size
-    peak = valu_peak_gcups(4)
+    achieved = cells / (ev_ms * 1e6)          # GCUPS of the one kernel launch per step
+    tflops = achieved * FLOPS_PER_CELL["squared"] / 1e3
+    issue_peak = valu_peak_gcups(4)           # GCUPS at 2 VALU instr / SIMD / quad-cycle
     R, T, W, KS, XL = P.sdtw_variant_info(variant)
     gc = cost.cpu().numpy()
     ge = end.cpu().numpy()
+    # shader clock while the same launch keeps the GPU busy (outside the timed
+    # steps); the roofline at the clock actually run is peak x clock / 2.4 GHz
+    sclk = sample_sclk(step, 80, torch)
+    at_clk = (PEAK_GHZ / sclk["ghz"]) if sclk else None
     kernel_tag = "sdtw_fwd_512x2000_vs_100k"
     out = {
         "metric": "sDTW GCUPS, 512x2000 queries vs 1e5 reference (FP32, squared cost)",
@@ -526,27 +655,46 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "queries": w.batch, "query_len": 2000,
                    "ref_len": w.ref_len, "cost": "squared", "cells": cells,
+                   "digest": workloads.digest(w),
                    "variant": {"rows_per_lane": R, "tile_cols": T, "waves": W,
                                "steps_per_barrier": KS,
                                "lane_exchange": "lds" if XL else "dpp"},
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "GCUPS",
-                     "frac": achieved / peak, "traffic": measured_traffic(kernel_tag),
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic(kernel_tag),
+                     "flops_per_cell": FLOPS_PER_CELL["squared"],
+                     "peak_basis": "MI355X FP32 vector peak: 256 CUs x 2.4 GHz, an FMA "
+                                   "counted as two flops; a cell is 5 flops (sub, mul, "
+                                   "two compares, add) in 4 VALU instructions, so this "
+                                   "kernel's ceiling on this basis is 5/8 = 0.625",
                      "kernel": f"sdtw_fwd_kernel<{R},{T},{W},{KS},{XL},squared>",
-                     "kernel_ms": ev_ms,
-                     "peak_basis": "256 CU x 128 lanes/clk (VALU dual issue) x 2.4 GHz / "
-                                   "4 VALU ops per cell",
-                     "single_issue_peak": valu_peak_gcups(4, lanes=64),
+                     "kernel_ms": ev_ms, "gcups": achieved,
+                     "issue": {"achieved_gcups": achieved, "peak_gcups": issue_peak,
+                               "frac": achieved / issue_peak,
+                               "basis": "4 VALU instructions per cell; 256 CUs x 4 SIMDs x "
+                                        "16 lanes x 2 instructions per quad-cycle x 2.4 GHz "
+                                        "= 78.6 T lane-instructions/s",
+                               "single_issue_peak_gcups": valu_peak_gcups(4, lanes=64)},
+                     "sclk_measured": sclk,
+                     "frac_at_measured_sclk": (tflops / PEAK_FP32_TFLOPS * at_clk)
+                     if at_clk else None,
+                     "issue_frac_at_measured_sclk": (achieved / issue_peak * at_clk)
+                     if at_clk else None,
                      "device_cus": props.multi_processor_count},
+        "gsps": float(w.lens.sum()) / (wall_ms * 1e6),
+        "gsps_note": "the paper's throughput unit (Eq. (3)): query samples processed "
+                     "per second, in 1e9",
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, gc, ge)
     if not args.no_extra:
         del ws
         torch.cuda.empty_cache()
-        out["batched"] = batched_leg(P, torch, steps=3, warmup=1)
-        out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1)
-        out["long_ref"] = long_ref_leg(P, torch, variant, steps=2, warmup=1)
+        ol = not args.no_cpu_baseline
+        out["batched"] = batched_leg(P, torch, steps=3, warmup=1, oracle_legs=ol)
+        out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1, oracle_legs=ol)
+        out["long_ref"] = long_ref_leg(P, torch, variant, steps=2, warmup=1, oracle_legs=ol)
         out["f16"] = f16_leg(P, torch, steps=5, warmup=1)
         out["pruned"] = pruned_leg(P, torch, gc, ge, steps=5, warmup=1)
         out["pruned"]["speed_vs_exact_kernel"] = ev_ms / out["pruned"]["kernel_ms"]

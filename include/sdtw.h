@@ -84,15 +84,33 @@ enum {
 #define SDTW_MAX_REF_LEN ((int64_t)1 << 30)
 
 /*
- * Bytes of device workspace sdtw_forward needs for this batch (flags as
- * passed to sdtw_forward).  Returns 0 on invalid arguments.
- * The workspace holds the per-query offset table, one DP row per query in
- * flight (it carries the last row of a row pass to the next pass for queries
- * longer than one pass; cost and end_pos are reduced on chip) and, for the
- * persistent form, the work queue.
+ * Bytes of device workspace sdtw_forward needs for this batch, with `flags`
+ * as passed to sdtw_forward and tile `variant` (-1: the variant the library
+ * picks for this batch, as sdtw_forward does with variant -1).  Returns 0 on
+ * invalid arguments or an unknown variant.
+ * The workspace holds the offset and slot tables of large batches, the
+ * persistent form's work counter and processing order, and a row buffer of
+ * ceil(ref_len / 64) * 64 floats per slot that carries the last DP row of a
+ * row pass to the next pass.  A pass covers 64 * R * W query rows (R rows per
+ * lane, W wavefronts per query: sdtw_variant_info); the plain launch gives a
+ * slot to each query longer than one pass, the persistent launch one to each
+ * of its workgroups when some query is.  A batch whose queries all fit in
+ * one pass needs no row buffer.  cost and end_pos are reduced on chip.
  */
 SDTW_API size_t sdtw_forward_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
-                                    int64_t ref_len, int32_t flags);
+                                    int64_t ref_len, int32_t flags, int32_t variant);
+
+/*
+ * Bytes of one workspace that serves every call of the differentiable path
+ * on this batch: sdtw_forward with `flags` and the library's variant choice,
+ * and, when flags has SDTW_F_CHECKPOINT, sdtw_backward and sdtw_align with
+ * checkpoints every `ckpt_every` columns (the largest of their sizes; the
+ * calls leave nothing in the workspace that a later call reads, so one
+ * buffer can serve them in turn on one stream).  Returns 0 on invalid
+ * arguments.
+ */
+SDTW_API size_t sdtw_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
+                                     int64_t ref_len, int32_t flags, int32_t ckpt_every);
 
 /*
  * Number of float32 entries of the checkpoint buffer for this batch and
@@ -126,8 +144,8 @@ SDTW_API size_t sdtw_checkpoint_floats(const int32_t *h_query_lens, int32_t batc
  *                multiple of 16, when checkpointing, else ignored
  *   variant      kernel tile variant (0 <= variant < sdtw_variant_count()),
  *                or -1 to let the library choose
- *   workspace    device, >= sdtw_forward_workspace_bytes(...) bytes,
- *                256-byte aligned
+ *   workspace    device, >= sdtw_forward_workspace_bytes(..., flags, variant)
+ *                bytes, 256-byte aligned (SDTW_ERR_WORKSPACE if smaller)
  *   stream       hipStream_t or NULL
  */
 SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
@@ -181,7 +199,7 @@ SDTW_API int sdtw_forward_u8(const float *queries, const int32_t *h_query_lens,
  * unable to lie on the warp path and costs +inf (no multiplication);
  * otherwise the cost is t*t, as for SDTW_COST_SQUARED.  Everything else is
  * sdtw_forward's: the same DP, outputs, variants and workspace
- * (sdtw_forward_workspace_bytes with the same flags).  The result is an
+ * (sdtw_forward_workspace_bytes with the same flags and variant).  The result is an
  * approximation of the squared-cost sDTW: cost[b] >= the exact cost, equal
  * whenever some optimal path has every |t| <= prune_tau (always for
  * prune_tau = +inf); a query with no such path gets +inf and end_pos 0.

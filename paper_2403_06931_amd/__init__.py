@@ -14,7 +14,7 @@ from .api import (SDTW_COST_ABSOLUTE, SDTW_COST_SQUARED, SDTW_F_CHECKPOINT,  # n
                   sdtw_forward_f16, sdtw_forward_f16_workspace_bytes, sdtw_forward_pruned,
                   sdtw_forward_u8, sdtw_forward_u8_workspace_bytes,
                   sdtw_forward_workspace_bytes, sdtw_variant_count, sdtw_variant_info,
-                  sdtw_znorm, sdtw_znorm_workspace_bytes, workspace)
+                  sdtw_workspace_bytes, sdtw_znorm, sdtw_znorm_workspace_bytes, workspace)
 from .graph import ForwardGraph  # noqa: F401,E402
 from .autograd import SDTWFunction, sdtw  # noqa: F401,E402
 from . import autotune  # noqa: F401,E402

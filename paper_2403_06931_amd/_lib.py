@@ -47,8 +47,11 @@ def _load():
     lib.sdtw_default_variant.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.sdtw_default_variant.restype = ctypes.c_int32
     lib.sdtw_forward_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64,
-                                                 ctypes.c_int32]
+                                                 ctypes.c_int32, ctypes.c_int32]
     lib.sdtw_forward_workspace_bytes.restype = ctypes.c_size_t
+    lib.sdtw_workspace_bytes.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_int32]
+    lib.sdtw_workspace_bytes.restype = ctypes.c_size_t
     lib.sdtw_checkpoint_floats.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32]
     lib.sdtw_checkpoint_floats.restype = ctypes.c_size_t
     lib.sdtw_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,

@@ -75,7 +75,7 @@ def time_variant(variant: int, queries, h_lens, query_lens, reference, cost_kind
     dev = queries.device
     if workspace_buf is None:
         workspace_buf = api.workspace(api.sdtw_forward_workspace_bytes(h, reference.numel(),
-                                                                       flags), dev)
+                                                                       flags, variant), dev)
     cost = torch.empty(h.size, dtype=torch.float32, device=dev)
     end = torch.empty(h.size, dtype=torch.int64, device=dev)
     kw = dict(cost=cost, end_pos=end, variant=variant, flags=flags, workspace_buf=workspace_buf,
@@ -101,8 +101,10 @@ def tune(queries, h_lens, query_lens, reference, cost_kind: int = 0, flags: int 
     h = api._host_lens(h_lens)
     if candidates is None:
         candidates = range(api.sdtw_variant_count())
-    ws = api.workspace(api.sdtw_forward_workspace_bytes(h, reference.numel(), flags),
-                       queries.device)
+    candidates = [int(v) for v in candidates]
+    # one workspace large enough for every candidate tile
+    ws = api.workspace(max(api.sdtw_forward_workspace_bytes(h, reference.numel(), flags, v)
+                           for v in candidates), queries.device)
     results = {}
     for v in candidates:
         results[int(v)] = time_variant(int(v), queries, h, query_lens, reference, cost_kind,

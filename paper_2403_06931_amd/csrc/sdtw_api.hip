@@ -64,19 +64,15 @@ bool ref_ok(int64_t ref_len) { return ref_len >= 1 && ref_len <= SDTW_MAX_REF_LE
 
 int64_t row_stride_floats(int64_t ref_len) { return (int64_t)align_up((size_t)ref_len, 64); }
 
-// Row-buffer slots of the persistent form (one per resident workgroup); the
-// grid launched never exceeds this, so the workspace size does not depend on
-// the device.
-constexpr int kMaxPersistentSlots = 4096;
-
-int64_t persistent_slots(int32_t batch) { return std::min<int64_t>(batch, kMaxPersistentSlots); }
-
 // Batches up to this size let each workgroup sum the lengths before its
 // query instead of running the offset-table kernel first.
 constexpr int32_t kInKernelOffsetBatch = 16384;
 
+// Forward workspace: offset and slot tables (used above kInKernelOffsetBatch
+// queries), the persistent form's work counter and processing order, and the
+// row buffer that carries the last row of a row pass to the next pass.
 struct FwdLayout {
-  size_t offsets, rowbuf, queue, order, total;
+  size_t offsets, ranks, queue, order, rowbuf, total;
   int64_t slots;
 };
 
@@ -85,6 +81,8 @@ FwdLayout fwd_layout(int32_t batch, int64_t ref_len, int32_t flags, int64_t slot
   size_t at = 0;
   L.offsets = at;
   at = align_up(at + sizeof(int64_t) * ((size_t)batch + 1), kAlign);
+  L.ranks = at;
+  at = align_up(at + sizeof(int32_t) * (size_t)batch, kAlign);
   L.queue = at;
   at = align_up(at + sizeof(int32_t) * 4, kAlign);
   L.order = at;
@@ -106,7 +104,7 @@ struct U8Layout {
 
 U8Layout u8_layout(int32_t batch, int64_t total_rows, int64_t ref_len) {
   U8Layout L{};
-  L.fwd = fwd_layout(batch, ref_len, 0, batch);
+  L.fwd = fwd_layout(batch, ref_len, 0, batch);   // one row-buffer slot per query
   size_t at = L.fwd.total;
   L.qcodes = at;
   at = align_up(at + (size_t)total_rows, kAlign);
@@ -122,6 +120,26 @@ U8Layout u8_layout(int32_t batch, int64_t total_rows, int64_t ref_len) {
 }
 
 constexpr int kU8Codes = 3;             // forward_impl's kind for the code DP
+
+// Persistent grid: eight waves per CU (two per SIMD), at most one workgroup
+// per query.
+int64_t persistent_grid_for(const Variant& v, int32_t batch, int cus) {
+  return std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)cus * 8 / v.W));
+}
+
+// Row-buffer slots a forward launch of variant v needs: the plain launch
+// gives one to each query longer than one pass of the tile (64 R W rows),
+// indexed by its rank among those queries; the persistent launch one to each
+// workgroup of its grid, if any query needs a second pass.  Queries that fit
+// in one pass never touch the row buffer.
+int64_t fwd_slots(const Variant& v, const int32_t* h_lens, int32_t batch, int32_t flags,
+                  int cus) {
+  const int64_t rows = 64LL * v.R * v.W;
+  int64_t multi = 0;
+  for (int32_t b = 0; b < batch; ++b) multi += h_lens[b] > rows ? 1 : 0;
+  if (flags & SDTW_F_PERSISTENT) return multi > 0 ? persistent_grid_for(v, batch, cus) : 0;
+  return multi;
+}
 
 int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
   if (every < 1) return -1;
@@ -173,12 +191,6 @@ int device_cus() {
     v = 256;
   if (dev >= 0 && dev < kMaxDevices) cached[dev] = v;
   return v;
-}
-
-// Persistent grid: eight waves per CU (two per SIMD), capped by the number of
-// row-buffer slots at the call site.
-int persistent_grid_for(const Variant& v, int cus) {
-  return std::max(1, cus * 8 / v.W);
 }
 
 int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t flags, int cus) {
@@ -317,7 +329,10 @@ int bwd_walk(sdtw::BwdParams& p, const BwdLayout& L, const int32_t* query_lens, 
   int64_t* offs = const_cast<int64_t*>(p.offsets);
   int rc;
   {
-    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    int32_t rows = 0;
+    int32_t* ranks = nullptr;
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs, (void*)&rows,
+                    (void*)&ranks};
     rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
                 dim3(sdtw::kScanThreads), args, stream);
     if (rc != SDTW_OK) return rc;
@@ -401,10 +416,14 @@ int32_t sdtw_default_variant(const int32_t* h_query_lens, int32_t batch, int64_t
 }
 
 size_t sdtw_forward_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
-                                    int32_t flags) {
+                                    int32_t flags, int32_t variant_id) {
   if (!lens_ok(h_query_lens, batch, nullptr, nullptr) || !ref_ok(ref_len)) return 0;
   if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return 0;
-  const int64_t slots = (flags & SDTW_F_PERSISTENT) ? persistent_slots(batch) : batch;
+  if (variant_id < -1 || variant_id >= variant_count()) return 0;
+  const int cus = device_cus();
+  const int vid = variant_id >= 0 ? variant_id
+                                  : pick_variant(h_query_lens, batch, ref_len, flags, cus);
+  const int64_t slots = fwd_slots(variant(vid), h_query_lens, batch, flags, cus);
   return fwd_layout(batch, ref_len, flags, slots).total;
 }
 
@@ -444,20 +463,23 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
   }
   if (variant_id < -1 || variant_id >= variant_count()) return SDTW_ERR_UNSUPPORTED;
   const bool persistent = (flags & SDTW_F_PERSISTENT) != 0;
-  const int64_t slots = persistent ? persistent_slots(batch) : batch;
+  const int cus = device_cus();
+  const int vid = variant_id >= 0 ? variant_id
+                                  : pick_variant(h_query_lens, batch, ref_len, flags, cus);
+  const Variant& v = variant(vid);
+  // the uint8-code kernel indexes the row buffer by query
+  const int64_t slots = cost_kind == kU8Codes ? batch
+                                              : fwd_slots(v, h_query_lens, batch, flags, cus);
   const FwdLayout L = fwd_layout(batch, ref_len, flags, slots);
   if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
-
-  const int vid = variant_id >= 0 ? variant_id
-                                  : pick_variant(h_query_lens, batch, ref_len, flags, device_cus());
-  const Variant& v = variant(vid);
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   char* ws = static_cast<char*>(workspace);
 
   FwdParams p{};
   p.queries = queries;
   p.lens = query_lens;
-  p.offsets = reinterpret_cast<int64_t*>(ws + L.offsets);
+  p.offsets = nullptr;
+  p.ranks = nullptr;
   p.reference = reference;
   p.rowbuf = reinterpret_cast<float*>(ws + L.rowbuf);
   p.cost = cost;
@@ -475,14 +497,18 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
   const bool pruned = cost_kind == sdtw::kPruned;
 
   if (batch > kInKernelOffsetBatch) {
+    // offset and row-buffer slot tables; smaller batches let each workgroup
+    // sum the lengths before its query instead
     int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
-    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    int32_t* ranks = reinterpret_cast<int32_t*>(ws + L.ranks);
+    int32_t rows = 64 * v.R * v.W;
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs, (void*)&rows,
+                    (void*)&ranks};
     int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
                     dim3(sdtw::kScanThreads), args, stream);
     if (rc != SDTW_OK) return rc;
     p.offsets = offs;
-  } else {
-    p.offsets = nullptr;            // each workgroup sums the lengths before its query
+    p.ranks = ranks;
   }
   if (cost_kind == kU8Codes) {
     void* args[] = {(void*)&p};
@@ -497,7 +523,7 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
     int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_order_kernel), dim3(1),
                     dim3(sdtw::kScanThreads), oargs, stream);
     if (rc != SDTW_OK) return rc;
-    const int grid = (int)std::min<int64_t>(L.slots, persistent_grid_for(v, device_cus()));
+    const int grid = (int)persistent_grid_for(v, batch, cus);
     void* args[] = {(void*)&p};
     return launch(pruned ? v.pruned[1] : v.persistent[cost_kind][ck], dim3(grid),
                   dim3(64 * v.W), args, stream);
@@ -637,7 +663,10 @@ int sdtw_forward_f16(const float* queries, const int32_t* h_query_lens,
   p.ref_len = (int32_t)ref_len;
   if (batch > kInKernelOffsetBatch) {
     int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
-    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs};
+    int32_t rows = 0;
+    int32_t* ranks = nullptr;
+    void* args[] = {(void*)&query_lens, (void*)&batch, (void*)&offs, (void*)&rows,
+                    (void*)&ranks};
     int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_offsets_kernel), dim3(1),
                     dim3(sdtw::kScanThreads), args, stream);
     if (rc != SDTW_OK) return rc;
@@ -762,6 +791,16 @@ int sdtw_align(const float* queries, const int32_t* h_query_lens, const int32_t*
   return launch(reinterpret_cast<const void*>(&sdtw::sdtw_align_start_kernel),
                 dim3((batch + sdtw::kInitThreads - 1) / sdtw::kInitThreads),
                 dim3(sdtw::kInitThreads), args, stream);
+}
+
+size_t sdtw_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
+                            int32_t flags, int32_t ckpt_every) {
+  const size_t fwd = sdtw_forward_workspace_bytes(h_query_lens, batch, ref_len, flags, -1);
+  if (fwd == 0 || !(flags & SDTW_F_CHECKPOINT)) return fwd;
+  const size_t bwd = sdtw_backward_workspace_bytes(h_query_lens, batch, ref_len, ckpt_every);
+  const size_t aln = sdtw_align_workspace_bytes(h_query_lens, batch, ref_len, ckpt_every);
+  if (bwd == 0 || aln == 0) return 0;
+  return std::max({fwd, bwd, aln});
 }
 
 size_t sdtw_znorm_workspace_bytes(const int32_t* h_lens, int32_t batch) {

@@ -53,8 +53,11 @@ struct FwdParams {
   const float* queries;     // packed
   const int32_t* lens;      // [batch]
   const int64_t* offsets;   // [batch + 1] exclusive prefix sum of lens
+  const int32_t* ranks;     // [batch] row-buffer slot of each query, with offsets
   const float* reference;   // [ref_len]
-  float* rowbuf;            // [slots][row_stride]
+  float* rowbuf;            // [slots][row_stride]: one slot per query that needs
+                            // several row passes (plain launch) or per workgroup
+                            // (persistent launch)
   float* cost;              // [batch]   (written by the argmin kernel)
   int64_t* end_pos;         // [batch]
   float* ckpt;              // checkpoint columns, or nullptr
@@ -546,31 +549,56 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   }
 }
 
-// Offset of query b in the packed batch: read from the offset table when the
-// host asked for one (large batches), else summed by the workgroup.  No
-// thread-dependent branch (a loop of the persistent kernel holds barriers).
-__device__ __forceinline__ int64_t query_offset(const FwdParams& p, int b) {
-  if (p.offsets != nullptr) return p.offsets[b];
+// Where query b sits: its offset in the packed batch and, for the plain
+// launch, its row-buffer slot (the number of earlier queries longer than
+// `rows`, one pass of the tile; a query that fits in one pass never touches
+// the row buffer).  Read from the tables the host asked for (large batches),
+// else summed by the workgroup.  No thread-dependent branch (a loop of the
+// persistent kernel holds barriers).
+struct QueryPos {
+  int64_t off;
+  int32_t slot;
+};
+
+__device__ __forceinline__ QueryPos query_pos(const FwdParams& p, int b, int rows) {
+  if (p.offsets != nullptr)
+    return QueryPos{p.offsets[b], p.ranks != nullptr ? p.ranks[b] : 0};
   __shared__ unsigned long long s_off;
-  if (wave_id() == 0) s_off = 0;
+  __shared__ int s_slot;
+  if (wave_id() == 0) {
+    s_off = 0;
+    s_slot = 0;
+  }
   __syncthreads();
   unsigned long long acc = 0;
-  for (int k = threadIdx.x; k < b; k += blockDim.x) acc += (unsigned long long)p.lens[k];
+  int cnt = 0;
+  for (int k = threadIdx.x; k < b; k += blockDim.x) {
+    const int n = p.lens[k];
+    acc += (unsigned long long)n;
+    cnt += n > rows ? 1 : 0;
+  }
   atomicAdd(&s_off, acc);
+  atomicAdd(&s_slot, cnt);
   __syncthreads();
-  const int64_t off = uniform_i64(s_off);
+  const QueryPos qp{uniform_i64(s_off), __builtin_amdgcn_readfirstlane(s_slot)};
   __syncthreads();
-  return off;
+  return qp;
 }
 
-// One workgroup per query.
+__device__ __forceinline__ int64_t query_offset(const FwdParams& p, int b) {
+  return query_pos(p, b, 0x7fffffff).off;
+}
+
+// One workgroup per query; a query longer than one pass owns the row-buffer
+// slot of its rank among such queries.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) {
   using S = FwdShape<R, T, W, KS, XL>;
   __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
   const int b = blockIdx.x;
-  float* row = p.rowbuf + (int64_t)b * p.row_stride;
-  fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem);
+  const QueryPos qp = query_pos(p, b, S::ROWS);
+  float* row = p.rowbuf + (int64_t)qp.slot * p.row_stride;
+  fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, qp.off, row, s_mem);
 }
 
 // Binary16 form: one workgroup per pair of queries (2i, 2i+1), which must

@@ -9,29 +9,45 @@ namespace sdtw {
 
 // Exclusive prefix sum of the query lengths (offsets[0..batch]) in one
 // workgroup: each thread sums a contiguous chunk, the chunk sums are scanned
-// in LDS, then each thread writes its chunk's offsets.
+// in LDS, then each thread writes its chunk's offsets.  With ranks != nullptr
+// it also writes, per query, the number of earlier queries longer than
+// `rows` (the row-buffer slot of a query that needs several row passes).
 constexpr int kScanThreads = 1024;
 
 __global__ __launch_bounds__(kScanThreads) void sdtw_offsets_kernel(
-    const int32_t* __restrict__ lens, int32_t batch, int64_t* __restrict__ offsets) {
+    const int32_t* __restrict__ lens, int32_t batch, int64_t* __restrict__ offsets,
+    int32_t rows, int32_t* __restrict__ ranks) {
   __shared__ int64_t s_sum[kScanThreads];
+  __shared__ int32_t s_cnt[kScanThreads];
   const int tid = threadIdx.x;
   const int per = (batch + kScanThreads - 1) / kScanThreads;
   const int lo = min(batch, tid * per), hi = min(batch, lo + per);
   int64_t acc = 0;
-  for (int i = lo; i < hi; ++i) acc += lens[i];
+  int32_t cnt = 0;
+  for (int i = lo; i < hi; ++i) {
+    acc += lens[i];
+    cnt += lens[i] > rows ? 1 : 0;
+  }
   s_sum[tid] = acc;
+  s_cnt[tid] = cnt;
   __syncthreads();
   for (int d = 1; d < kScanThreads; d <<= 1) {
     const int64_t v = tid >= d ? s_sum[tid - d] : 0;
+    const int32_t c = tid >= d ? s_cnt[tid - d] : 0;
     __syncthreads();
     s_sum[tid] += v;
+    s_cnt[tid] += c;
     __syncthreads();
   }
   int64_t run = s_sum[tid] - acc;                      // exclusive prefix of this chunk
+  int32_t rank = s_cnt[tid] - cnt;
   for (int i = lo; i < hi; ++i) {
     offsets[i] = run;
     run += lens[i];
+    if (ranks != nullptr) {
+      ranks[i] = rank;
+      rank += lens[i] > rows ? 1 : 0;
+    }
   }
   if (tid == kScanThreads - 1) offsets[batch] = s_sum[tid];
 }

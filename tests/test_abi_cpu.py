@@ -95,18 +95,51 @@ def test_forward_rejects_invalid_arguments(L):
     assert _fwd(L, [3, 4], ws_bytes=16) == L.SDTW_ERR_WORKSPACE
 
 
+def _variant_of(shape):
+    import paper_2403_06931_amd as P
+    for v in range(P.sdtw_variant_count()):
+        if P.sdtw_variant_info(v) == shape:
+            return v
+    raise AssertionError(shape)
+
+
 def test_workspace_sizes(L):
     import paper_2403_06931_amd as P
-    lens = np.array([5, 7, 300], np.int32)
-    a = P.sdtw_forward_workspace_bytes(lens, 1000)
-    b = P.sdtw_forward_workspace_bytes(lens, 100000)
-    assert 0 < a < b
-    assert b >= 3 * 100000 * 4            # one last-row buffer per query
+    row = lambda m: -(-m // 64) * 64 * 4            # one row-buffer slot, bytes
+    small = _variant_of((8, 8, 1, 16, 1))           # 512 rows per pass
+    big = _variant_of((8, 8, 4, 32, 1))             # 2,048 rows per pass
+    lens = np.array([5, 7, 300, 2000, 600], np.int32)
+    # plain launch: one slot per query longer than one pass of the tile
+    a = P.sdtw_forward_workspace_bytes(lens, 100000, 0, small)
+    assert 2 * row(100000) <= a < 2 * row(100000) + 4096
+    b = P.sdtw_forward_workspace_bytes(lens, 100000, 0, big)
+    assert 0 < b < 4096                              # every query fits in one pass
+    assert P.sdtw_forward_workspace_bytes(lens, 1000, 0, small) < a
+    # library choice: the size of the variant the library would pick
+    d = P.sdtw_default_variant(lens, 100000, 0)
+    assert P.sdtw_forward_workspace_bytes(lens, 100000, 0) == \
+        P.sdtw_forward_workspace_bytes(lens, 100000, 0, d)
     assert P.sdtw_forward_workspace_bytes(np.array([0], np.int32), 10) == 0
     assert P.sdtw_forward_workspace_bytes(lens, 0) == 0
-    pers = P.sdtw_forward_workspace_bytes(np.full(10000, 300, np.int32), 1000,
-                                          P.SDTW_F_PERSISTENT)
-    assert pers < P.sdtw_forward_workspace_bytes(np.full(10000, 300, np.int32), 1000)
+    assert P.sdtw_forward_workspace_bytes(lens, 1000, 0, 10**6) == 0
+    assert P.sdtw_forward_workspace_bytes(lens, 1000, 0, -2) == 0
+    # persistent launch: one slot per workgroup of its grid (at most 8 waves
+    # per CU), and none when no query needs a second pass
+    many = np.full(10000, 300, np.int32)
+    assert P.sdtw_forward_workspace_bytes(many, 1000, P.SDTW_F_PERSISTENT, small) < 10000 * 16 + 4096
+    many[7] = 3000
+    pers = P.sdtw_forward_workspace_bytes(many, 1000, P.SDTW_F_PERSISTENT, small)
+    assert pers >= 256 * 8 * row(1000) and pers < 256 * 8 * row(1000) + 2 * 10000 * 8 + 4096
+    plain = P.sdtw_forward_workspace_bytes(many, 1000, 0, small)
+    assert row(1000) <= plain < row(1000) + 10000 * 16
+    # one workspace for the whole differentiable path
+    ck = P.SDTW_F_CHECKPOINT
+    all_ = P.sdtw_workspace_bytes(lens, 50000, ck, 1024)
+    assert all_ >= P.sdtw_forward_workspace_bytes(lens, 50000, ck)
+    assert all_ >= P.sdtw_backward_workspace_bytes(lens, 50000, 1024)
+    assert all_ >= P.sdtw_align_workspace_bytes(lens, 50000, 1024)
+    assert P.sdtw_workspace_bytes(lens, 50000, 0, 0) == P.sdtw_forward_workspace_bytes(lens, 50000)
+    assert P.sdtw_workspace_bytes(lens, 50000, ck, 24) == 0
     # checkpoint columns: ceil(M/K) - 1 per query row
     assert P.sdtw_checkpoint_floats(lens, 1000, 256) == lens.sum() * 3
     assert P.sdtw_checkpoint_floats(lens, 1024, 256) == lens.sum() * 3
@@ -252,7 +285,7 @@ def test_forward_u8_validation(L):
     import paper_2403_06931_amd as P
     FAKE = 1 << 20
     h = np.ascontiguousarray([10, 12], dtype=np.int32)
-    assert P.sdtw_forward_u8_workspace_bytes(h, 1000) > P.sdtw_forward_workspace_bytes(h, 1000)
+    assert P.sdtw_forward_u8_workspace_bytes(h, 1000) > P.sdtw_forward_workspace_bytes(h, 1000, 0, 0)
     assert P.sdtw_forward_u8_workspace_bytes(np.array([40000], np.int32), 1000) > 0
     call = lambda hh=h, **k: L.lib.sdtw_forward_u8(
         _vp(k.get("q", FAKE)), _vp(hh.ctypes.data), _vp(FAKE), hh.size, _vp(FAKE), 100,
@@ -265,3 +298,52 @@ def test_forward_u8_validation(L):
     assert call(wsb=16) == L.SDTW_ERR_WORKSPACE
     assert call(v=10_000) == L.SDTW_ERR_UNSUPPORTED
     assert call(np.ascontiguousarray([5, 0], dtype=np.int32)) == L.SDTW_ERR_INVALID_ARG
+
+
+def test_binding_checks_sizes_before_any_call():
+    """The Python binding compares every tensor's dtype and size with what the
+    host lengths imply before calling the library (a short buffer would be
+    written out of bounds on the GPU), and reports it the same way with or
+    without a GPU."""
+    import torch
+
+    import paper_2403_06931_amd as P
+    h = np.array([3, 5], np.int32)
+    q = torch.zeros(8)
+    l = torch.from_numpy(h)
+    r = torch.zeros(100)
+
+    def raises(fn, what):
+        with pytest.raises(ValueError, match=what):
+            fn()
+    raises(lambda: P.sdtw_forward(torch.zeros(7), h, l, r), "queries must hold exactly 8")
+    raises(lambda: P.sdtw_forward(q, h, torch.from_numpy(h[:1].copy()), r),
+           "query_lens must hold exactly 2")
+    raises(lambda: P.sdtw_forward(q, h, l.to(torch.int64), r), "query_lens must be torch.int32")
+    raises(lambda: P.sdtw_forward(q.double(), h, l, r), "queries must be torch.float64|queries must be torch.float32")
+    raises(lambda: P.sdtw_forward(q, h, l, torch.zeros(0)), "reference must hold at least one")
+    raises(lambda: P.sdtw_forward(q, h, l, r, cost=torch.zeros(1)), "cost must hold at least 2")
+    raises(lambda: P.sdtw_forward(q, h, l, r, end_pos=torch.zeros(2)), "end_pos must be torch.int64")
+    raises(lambda: P.sdtw_forward(q, h, l, r, ckpt=None, ckpt_every=32,
+                                  flags=P.SDTW_F_CHECKPOINT), "ckpt is required")
+    raises(lambda: P.sdtw_forward(q, h, l, r, ckpt=torch.zeros(5), ckpt_every=32,
+                                  flags=P.SDTW_F_CHECKPOINT), "ckpt must hold at least 24")
+    raises(lambda: P.sdtw_backward(q, h, l, r, 0, torch.zeros(3), torch.zeros(2),
+                                   torch.zeros(2, dtype=torch.int64), torch.zeros(24), 32),
+           "grad_cost must hold exactly 2")
+    raises(lambda: P.sdtw_backward(q, h, l, r, 0, torch.zeros(2), torch.zeros(2),
+                                   torch.zeros(2, dtype=torch.int64), torch.zeros(20), 32),
+           "ckpt must hold at least 24")
+    raises(lambda: P.sdtw_backward(q, h, l, r, 0, torch.zeros(2), torch.zeros(2),
+                                   torch.zeros(2, dtype=torch.int64), torch.zeros(24), 32,
+                                   grad_reference=torch.zeros(99)),
+           "grad_reference must hold at least 100")
+    raises(lambda: P.sdtw_align(q, h, l, r, 0, torch.zeros(1),
+                                torch.zeros(2, dtype=torch.int64), torch.zeros(24), 32),
+           "cost must hold at least 2")
+    raises(lambda: P.sdtw_forward_u8(q, h, l, r, codebook=torch.zeros(1)),
+           "codebook must hold at least 2")
+    raises(lambda: P.sdtw_znorm(torch.zeros(9), h, l), "x must hold exactly 8")
+    raises(lambda: P.sdtw_znorm(q, h, l, out=torch.zeros(9)), "out must hold exactly 8")
+    # right sizes: the remaining complaint is the device
+    raises(lambda: P.sdtw_forward(q, h, l, r), "must be a CUDA tensor")

@@ -117,3 +117,58 @@ def test_long_reference_sampled(kind):
     sub = w.subset(idx)
     want_c, want_e = oracle.sdtw_f32(sub.queries, sub.lens, sub.reference, kind)
     assert_bit_exact(c[idx], e[idx], want_c, want_e, f"2M reference kind {kind}")
+
+
+def _all_variants_bit_exact(w, kind):
+    want_c, want_e = oracle.sdtw_f32(w.queries, w.lens, w.reference, kind)
+    for v in _variants():
+        c, e = gpu_forward(w, kind, variant=v)
+        assert_bit_exact(c, e, want_c, want_e, f"{w.name} kind {kind} variant {v}")
+    return want_c, want_e
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_small_integer_ties_all_variants(kind):
+    """Small-integer queries and references: exact ties in the cell costs, in
+    every three-way minimum and along the last row, so the end position must
+    be the first minimiser (the smallest index) on every variant.  A second
+    batch uses a periodic reference in which each query occurs many times at
+    cost 0."""
+    rng = np.random.default_rng(404 + kind)
+    lens = [1, 3, 64, 65, 200, 513, 1100, 2049]
+    ref = rng.integers(-2, 3, 3001).astype(np.float32)
+    qs = rng.integers(-2, 3, sum(lens)).astype(np.float32)
+    w = workloads.Workload("small-integers", qs, np.array(lens, np.int32), ref, (kind,),
+                           np.full(len(lens), -1, np.int64))
+    want_c, want_e = _all_variants_bit_exact(w, kind)
+    # the data do tie: some last row attains its minimum more than once
+    ties = 0
+    for b in range(2):
+        row = oracle.last_row_f32(w.query(b), ref, kind)
+        ties += int(np.count_nonzero(row == row.min()) > 1)
+    assert ties > 0
+
+    period = np.array([0, 1, 2, 1, -1, -2, 0, 2], np.float32)
+    ref = np.tile(period, 400)
+    lens = [5, 8, 30, 64, 129, 700]
+    qs = np.concatenate([np.tile(period, n // 8 + 2)[3:3 + n] for n in lens]).astype(np.float32)
+    w = workloads.Workload("periodic", qs, np.array(lens, np.int32), ref, (kind,),
+                           np.full(len(lens), -1, np.int64))
+    want_c, want_e = _all_variants_bit_exact(w, kind)
+    assert np.all(want_c == 0)
+
+
+@pytest.mark.parametrize("kind,scale", [(0, 1e-20), (0, 3e-19), (1, 2e-39)])
+def test_subnormal_values_all_variants(kind, scale):
+    """Inputs scaled so that cell costs (squared: (q - r)^2 near 1e-40) or the
+    inputs themselves (absolute: values near 1e-39) are subnormal binary32
+    numbers; both sides keep subnormals, so results stay bit-exact."""
+    w = workloads.make_random(6, [1, 2, 40, 300, 700, 1500], 2500, seed=606, excerpt_every=0)
+    w.queries = (w.queries.astype(np.float64) * scale).astype(np.float32)
+    w.reference = (w.reference.astype(np.float64) * scale).astype(np.float32)
+    tiny = np.finfo(np.float32).tiny
+    t = (w.queries[:43, None] - w.reference[None, :]).astype(np.float32)
+    c = (t * t).astype(np.float32) if kind == 0 else np.abs(t)
+    assert np.any((c > 0) & (c < tiny)), "no subnormal cell cost in the sample"
+    want_c, want_e = _all_variants_bit_exact(w, kind)
+    assert np.any((want_c > 0) & (want_c < tiny)), "no subnormal result"
