@@ -107,6 +107,12 @@ def measured_traffic(kernel_tag):
         return None
 
 
+def progress(msg):
+    """One line per finished step of the benchmark, on stderr (the JSON result
+    goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -626,7 +632,9 @@ def main():
         P.sdtw_forward(q, w.lens, l, r, P.SDTW_COST_SQUARED, cost=cost, end_pos=end,
                        variant=variant, workspace_buf=ws)
 
+    progress(f"headline variant {P.sdtw_variant_info(variant)} chosen")
     wall_ms, ev_ms = time_steps(step, args.steps, args.warmup, torch)
+    progress(f"headline timed: {ev_ms:.3f} ms per step")
     cells = w.cells
     value = cells / (wall_ms * 1e6)
     achieved = cells / (ev_ms * 1e6)          # GCUPS of the one kernel launch per step
@@ -686,21 +694,30 @@ def main():
         "gsps_note": "the paper's throughput unit (Eq. (3)): query samples processed "
                      "per second, in 1e9",
     }
+    progress(f"clock sampled: {sclk}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, gc, ge)
+        progress("cpu baseline done")
     if not args.no_extra:
         del ws
         torch.cuda.empty_cache()
         ol = not args.no_cpu_baseline
         out["batched"] = batched_leg(P, torch, steps=3, warmup=1, oracle_legs=ol)
+        progress("batched leg done")
         out["fwd_bwd"] = fwd_bwd_leg(P, torch, steps=5, warmup=1, oracle_legs=ol)
+        progress("fwd+bwd leg done")
         out["long_ref"] = long_ref_leg(P, torch, variant, steps=2, warmup=1, oracle_legs=ol)
+        progress("long-reference leg done")
         out["f16"] = f16_leg(P, torch, steps=5, warmup=1)
+        progress("binary16 leg done")
         out["pruned"] = pruned_leg(P, torch, gc, ge, steps=5, warmup=1)
         out["pruned"]["speed_vs_exact_kernel"] = ev_ms / out["pruned"]["kernel_ms"]
+        progress("pruned leg done")
         out["u8"] = u8_leg(P, torch, gc, ge, steps=5, warmup=1)
         out["u8"]["speed_vs_exact_kernel"] = ev_ms / out["u8"]["call_ms"]
+        progress("uint8 leg done")
         out["znorm"] = znorm_leg(P, torch, steps=20, warmup=3)
+        progress("normaliser leg done")
     print(json.dumps(out), flush=True)
 
 

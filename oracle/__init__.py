@@ -18,7 +18,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# SDTW_ORACLE_LIBRARY may name another build of the same source (for
+# example one built with sanitizers)
+_LIB_PATH = os.environ.get("SDTW_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 SQUARED = 0

@@ -8,7 +8,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsdtw.so")
+# SDTW_LIBRARY may name another build of the same library (for example one
+# whose host code is built with sanitizers)
+LIB_PATH = os.environ.get("SDTW_LIBRARY") or os.path.join(_HERE, "libsdtw.so")
 
 SDTW_COST_SQUARED = 0
 SDTW_COST_ABSOLUTE = 1

@@ -818,6 +818,42 @@ int sdtw_znorm(const float* x, const int32_t* h_lens, const int32_t* lens, int32
   if (L.chunks > INT32_MAX) return SDTW_ERR_UNSUPPORTED;
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   char* ws = static_cast<char*>(workspace);
+  if (batch <= sdtw::kZDirectBatch) {
+    // direct form: the host lists the long series (it knows their offsets)
+    sdtw::ZDirect d{};
+    int64_t off = 0;
+    int32_t long_chunks = 0;
+    bool fits = true;
+    for (int32_t b = 0; b < batch && fits; ++b) {
+      if (h_lens[b] > sdtw::kZWaveMax) {
+        if (d.nlong == sdtw::kZMaxLong) {
+          fits = false;
+          break;
+        }
+        const int32_t nch = (int32_t)sdtw::znorm_chunks_of(h_lens[b]);
+        d.lg[d.nlong] = sdtw::ZLong{off, b, h_lens[b], long_chunks, nch};
+        ++d.nlong;
+        long_chunks += nch;
+      }
+      off += h_lens[b];
+    }
+    if (fits) {
+      d.x = x;
+      d.z = z;
+      d.lens = lens;
+      d.part = reinterpret_cast<double*>(ws + L.part);
+      d.batch = batch;
+      d.short_wgs = (batch + sdtw::kZSeriesPerWG - 1) / sdtw::kZSeriesPerWG;
+      void* args[] = {(void*)&d};
+      int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_direct_kernel),
+                      dim3((unsigned)(d.short_wgs + long_chunks)), dim3(sdtw::kZThreads), args,
+                      stream);
+      if (rc != SDTW_OK || long_chunks == 0) return rc;
+      return launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_long_apply_kernel),
+                    dim3((unsigned)long_chunks), dim3(sdtw::kZThreads), args, stream);
+    }
+  }
+  // table form
   sdtw::ZParams p{};
   p.x = x;
   p.z = z;

@@ -434,14 +434,115 @@ __device__ __forceinline__ void fwd_pass_out(int out_k, const FwdParams& p,
   }
 }
 
+// One pass of query b: rows [prow0, prow0 + 64 RR W) held RR per lane.  The
+// tile schedule (delays, rings, barriers) does not depend on RR, so any RR
+// computes the same cells bit for bit; RR only decides how many rows a pass
+// covers and how they are spread over the lanes.
+template <int RR, int T, int W, int KS, int XL, int KIND, bool CKPT, typename V>
+__device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom& G, int pos,
+                                             int prow0, int pass_rows, bool last_pass,
+                                             const typename Val<V>::In* __restrict__ q,
+                                             const typename Val<V>::In* __restrict__ q2,
+                                             const V* prev_row, V* s_ref, V* s_hand,
+                                             V* s_slot) {
+  using S = FwdShape<RR, T, W, KS, XL>;
+  using In = typename Val<V>::In;
+  const int tid = threadIdx.x;
+  G.row0 = prow0 + pos * RR;                           // first row of this lane
+  LaneState<RR, T, V> L;
+#pragma unroll
+  for (int k = 0; k < RR; ++k) {
+    const bool in = G.row0 + k < G.n;
+    if constexpr (Val<V>::N == 1) {
+      L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : In(0), In(0));
+    } else {
+      L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : 0.0f, in ? q2[G.row0 + k] : 0.0f);
+    }
+    L.dl[k] = Val<V>::inf();
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) L.bot[t] = Val<V>::inf();
+  L.corner = Val<V>::inf();
+  L.ck_h = G.my_delay + G.tiles_per_ckpt - 1;          // reaches checkpoint 0 there
+  L.ck_k = 0;
+#pragma unroll
+  for (int k = 0; k < RR; ++k) L.ckv[k] = 0.0f;
+#pragma unroll
+  // (+inf, column 0): a row that is +inf throughout (an overflow) folds
+  // nothing and reports its first column, the smallest index attaining
+  // the minimum; any finite value replaces it
+  for (int h = 0; h < Val<V>::N; ++h) L.am[h] = ValIdx{inf_f32(), 0};
+  L.tau = 0.0f;
+  if constexpr (KIND == kPruned) L.tau = vgpr_copy(p.prune_tau);
+
+  // Row stored by this pass: the pass's last row (to the row buffer), or
+  // row N on the final pass (reduced on the fly).
+  G.final_pass = last_pass;
+  const int out_row = last_pass ? (G.n - 1 - prow0) : (pass_rows - 1);
+  const int out_pos = out_row / RR;
+  const int out_k = out_row - out_pos * RR;
+  const int out_wave = out_pos / kWave;
+  G.out_lane = out_pos - out_wave * kWave;
+  G.out_delay = S::LL * out_pos + out_wave * S::LAG;  // out lane's tile = step - out_delay
+
+  // +inf handoff rings and lane slots (a lane before its first tile must
+  // see +inf), a zeroed reference ring (so that those lanes compute on
+  // finite values, never on whatever the LDS held), then the first two
+  // intervals of reference and top boundary.
+  for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
+  for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
+  for (int e = tid; e < S::SR * T; e += S::THREADS) s_ref[e] = Val<V>::zero();
+  __syncthreads();
+  {
+    Stager<RR, T, W, KS, XL, V> st0, st1;
+    st0.load(p.reference, p.ref_len, prev_row, G.ntiles * T, 0, tid);
+    st1.load(p.reference, p.ref_len, prev_row, G.ntiles * T, KS, tid);
+    st0.commit(s_ref, s_hand, 0, tid);
+    st1.commit(s_ref, s_hand, KS, tid);
+  }
+  __syncthreads();
+
+  if (G.wave == out_wave) {
+    fwd_pass_out<0, RR, T, W, KS, XL, KIND, CKPT, V>(out_k, p, L, G, prev_row, s_ref, s_hand,
+                                                     s_slot);
+    if (last_pass) {
+      // every lane of the wave holds the result and stores it (no
+      // lane-dependent branch in a loop that holds barriers)
+#pragma unroll
+      for (int h = 0; h < Val<V>::N; ++h) {
+        if (h == 0 || b + h < p.batch) {
+          const ValIdx x = wave_argmin(L.am[h]);
+          p.cost[b + h] = x.v;
+          p.end_pos[b + h] = x.i;
+        }
+      }
+    }
+  } else {
+    fwd_pass<RR, T, W, KS, XL, KIND, CKPT, -1, V>(p, L, G, prev_row, s_ref, s_hand, s_slot);
+  }
+}
+
+// Rows per lane of the shortest tail pass fwd_query may use with R rows per
+// lane in its full passes (R itself: no tail form).
+template <int R>
+constexpr int tail_rows_min() {
+  return R >= 8 ? R / 4 : (R >= 4 ? R / 2 : R);
+}
+
 // Process every pass of query b (with f16x2 values: queries b and b+1, of
 // equal length, or b twice when it is the batch's last) with the team of W
 // waves of this workgroup and store cost and end position.  `row` is the
 // row-buffer slot (rows carried from one pass to the next, as V words).
-template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, typename V = float>
+// Full passes hold R rows per lane.  With RT < R the last pass, when its
+// rows fit, holds R/2 or (if RT allows) R/4 rows per lane instead: fewer
+// padding rows below row N for a query that is not a multiple of a pass
+// long, at a somewhat higher cost per cell.
+template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, typename V = float,
+          int RT = R>
 __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qoff,
                                           float* __restrict__ row, float* s_mem) {
   static_assert(!CKPT || Val<V>::N == 1, "checkpoints are binary32 only");
+  static_assert(RT == R || RT == R / 2 || RT == R / 4, "tail passes hold R/2 or R/4 rows");
   using S0 = FwdShape<R, T, W, KS, XL>;
   V* s_ref = reinterpret_cast<V*>(s_mem);
   V* s_hand = s_ref + S0::SR * T;
@@ -472,80 +573,25 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
 
   for (int pass = 0; pass < npass; ++pass) {
     const int prow0 = pass * S::ROWS;                  // first row of this pass
-    G.row0 = prow0 + pos * R;                          // first row of this lane
-    LaneState<R, T, V> L;
-#pragma unroll
-    for (int k = 0; k < R; ++k) {
-      const bool in = G.row0 + k < G.n;
-      if constexpr (Val<V>::N == 1) {
-        L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : In(0), In(0));
-      } else {
-        L.qv[k] = Val<V>::query(in ? q[G.row0 + k] : 0.0f, in ? q2[G.row0 + k] : 0.0f);
-      }
-      L.dl[k] = Val<V>::inf();
-    }
-#pragma unroll
-    for (int t = 0; t < T; ++t) L.bot[t] = Val<V>::inf();
-    L.corner = Val<V>::inf();
-    L.ck_h = G.my_delay + G.tiles_per_ckpt - 1;        // reaches checkpoint 0 there
-    L.ck_k = 0;
-#pragma unroll
-    for (int k = 0; k < R; ++k) L.ckv[k] = 0.0f;
-#pragma unroll
-    // (+inf, column 0): a row that is +inf throughout (an overflow) folds
-    // nothing and reports its first column, the smallest index attaining
-    // the minimum; any finite value replaces it
-    for (int h = 0; h < Val<V>::N; ++h) L.am[h] = ValIdx{inf_f32(), 0};
-    L.tau = 0.0f;
-    if constexpr (KIND == kPruned) L.tau = vgpr_copy(p.prune_tau);
-
-    // Row stored by this pass: the pass's last row (to the row buffer), or
-    // row N on the final pass (reduced on the fly).
     const bool last_pass = pass == npass - 1;
-    G.final_pass = last_pass;
-    const int out_row = last_pass ? (G.n - 1 - prow0) : (S::ROWS - 1);
-    const int out_pos = out_row / R;
-    const int out_k = out_row - out_pos * R;
-    const int out_wave = out_pos / kWave;
-    G.out_lane = out_pos - out_wave * kWave;
-    G.out_delay = S::LL * out_pos + out_wave * S::LAG;  // out lane's tile = step - out_delay
     const V* prev_row = pass > 0 ? reinterpret_cast<const V*>(row) : nullptr;
-
-    // +inf handoff rings and lane slots (a lane before its first tile must
-    // see +inf), a zeroed reference ring (so that those lanes compute on
-    // finite values, never on whatever the LDS held), then the first two
-    // intervals of reference and top boundary.
-    for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
-    for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
-    for (int e = tid; e < S::SR * T; e += S::THREADS) s_ref[e] = Val<V>::zero();
-    __syncthreads();
-    {
-      Stager<R, T, W, KS, XL, V> st0, st1;
-      st0.load(p.reference, p.ref_len, prev_row, G.ntiles * T, 0, tid);
-      st1.load(p.reference, p.ref_len, prev_row, G.ntiles * T, KS, tid);
-      st0.commit(s_ref, s_hand, 0, tid);
-      st1.commit(s_ref, s_hand, KS, tid);
-    }
-    __syncthreads();
-
-    if (G.wave == out_wave) {
-      fwd_pass_out<0, R, T, W, KS, XL, KIND, CKPT, V>(out_k, p, L, G, prev_row, s_ref, s_hand,
-                                                      s_slot);
-      if (last_pass) {
-        // every lane of the wave holds the result and stores it (no
-        // lane-dependent branch in a loop that holds barriers)
-#pragma unroll
-        for (int h = 0; h < Val<V>::N; ++h) {
-          if (h == 0 || b + h < p.batch) {
-            const ValIdx x = wave_argmin(L.am[h]);
-            p.cost[b + h] = x.v;
-            p.end_pos[b + h] = x.i;
-          }
+    if constexpr (RT < R) {
+      const int left = G.n - prow0;                    // rows of this pass, uniform
+      if constexpr (RT <= R / 4) {
+        if (last_pass && left <= kWave * W * (R / 4)) {
+          fwd_one_pass<R / 4, T, W, KS, XL, KIND, CKPT, V>(p, b, G, pos, prow0, left, true, q,
+                                                           q2, prev_row, s_ref, s_hand, s_slot);
+          continue;
         }
       }
-    } else {
-      fwd_pass<R, T, W, KS, XL, KIND, CKPT, -1, V>(p, L, G, prev_row, s_ref, s_hand, s_slot);
+      if (last_pass && left <= kWave * W * (R / 2)) {
+        fwd_one_pass<R / 2, T, W, KS, XL, KIND, CKPT, V>(p, b, G, pos, prow0, left, true, q, q2,
+                                                         prev_row, s_ref, s_hand, s_slot);
+        continue;
+      }
     }
+    fwd_one_pass<R, T, W, KS, XL, KIND, CKPT, V>(p, b, G, pos, prow0, S::ROWS, last_pass, q, q2,
+                                                 prev_row, s_ref, s_hand, s_slot);
   }
 }
 
@@ -649,7 +695,9 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const Fw
     __syncthreads();
     if (item >= p.batch) break;
     const int b = __builtin_amdgcn_readfirstlane(p.order[item]);
-    fwd_query<R, T, W, KS, XL, KIND, CKPT>(p, b, query_offset(p, b), row, s_mem);
+    // a query's last pass may hold fewer rows per lane (not with checkpoints)
+    fwd_query<R, T, W, KS, XL, KIND, CKPT, float, CKPT ? R : tail_rows_min<R>()>(
+        p, b, query_offset(p, b), row, s_mem);
   }
 }
 

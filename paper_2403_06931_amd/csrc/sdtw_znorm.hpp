@@ -4,19 +4,32 @@
 // the population standard deviation.  Included by the API translation unit
 // only.
 //
-// Layout.  A series is cut into chunks of kZChunk elements; one 256-thread
-// workgroup owns a chunk and keeps it in registers (16 values per thread,
-// loads coalesced across the workgroup).  The per-chunk sum and the sum of
-// squared deviations from the chunk mean are reduced in binary64.  A series
-// of one chunk (every query of the paper's workloads) is finished by the same
-// workgroup: one HBM read and one write per element, which is the bound.  A
-// longer series (a reference) stores its chunk partials; a second kernel
-// combines them exactly in fixed order (sum of squares = sum over chunks of
-// the chunk's own sum plus n_k (mean_k - mean)^2) and writes z after reading
-// the chunk once more.  All reductions run in a fixed order, so results do
-// not depend on scheduling; z = (x - mean) * (1/S) is formed in binary64
-// (one reciprocal per workgroup instead of a division per sample, 9 % faster
-// on 4,096 short series) and rounded once to binary32.
+// Statistics are reduced in binary64 in a fixed order, so results do not
+// depend on scheduling; z = (x - mean) * (1/S) is formed in binary64 (one
+// reciprocal per series instead of a division per sample) and rounded once to
+// binary32.  The data are read once and written once wherever a series fits
+// on one compute unit; that traffic (8 bytes per sample) is the bound.
+//
+// Direct form (batches of up to kZDirectBatch series with at most kZMaxLong
+// series longer than kZWaveMax):
+//   * one launch standardises every short series (up to kZWaveMax samples)
+//     with one wavefront each, the series held in registers (up to 64 per
+//     lane, loads coalesced across the wavefront) and both sums reduced by a
+//     butterfly within the wavefront: no barrier and no LDS.  A workgroup
+//     takes kZSeriesPerWG consecutive series and finds where they start by
+//     summing the lengths before them (a few kilobytes from L2), so no
+//     offset table and no extra launch is needed.  Workgroups past those
+//     take the chunks of the long series, which the host describes in the
+//     kernel arguments (it knows their offsets from the host lengths), and
+//     store each chunk's sum and sum of squared deviations;
+//   * a second launch, only when there are long series, combines a long
+//     series' chunk partials exactly in a fixed order (sum of squares = sum
+//     over chunks of the chunk's own sum plus n_k (mean_k - mean)^2) and
+//     standardises each chunk after reading it once more.
+// Table form (any batch): a one-workgroup index kernel builds element and
+// chunk offsets and the chunk -> series map, one workgroup per chunk of
+// kZChunk samples computes the chunk statistics (and finishes single-chunk
+// series), and the same combine-and-standardise step finishes the rest.
 #pragma once
 
 #include "sdtw_common.hpp"
@@ -209,6 +222,169 @@ __global__ __launch_bounds__(kZThreads) void sdtw_znorm_apply_kernel(const ZPara
   float v[kZPer];
   znorm_load(p, q, v);
   znorm_store(p, q, v, mean, sd);
+}
+
+// ------------------------------------------------------------ direct form
+
+constexpr int kZWavePer = 64;                        // samples per lane
+constexpr int kZWaveMax = kWave * kZWavePer;         // series standardised by one wave
+constexpr int kZSeriesPerWG = kZThreads / kWave;     // one wave per series
+constexpr int kZMaxLong = 32;                        // long series in the kernel arguments
+constexpr int32_t kZDirectBatch = 16384;
+static_assert(kZWaveMax == kZChunk, "a short series is one chunk of the table form");
+
+struct ZLong {
+  int64_t off;                  // first element of the series
+  int32_t b, n;                 // series index and length
+  int32_t c0, nch;              // its first chunk among the long chunks, chunk count
+};
+
+struct ZDirect {
+  const float* x;
+  float* z;
+  const int32_t* lens;
+  double* part;                 // [long chunks][2]
+  int32_t batch;
+  int32_t short_wgs;            // workgroups of the short series (first in the grid)
+  int32_t nlong;
+  ZLong lg[kZMaxLong];
+};
+
+// Sum over the 64 lanes of a wavefront: every lane ends with the same bits
+// (each step adds the same two values, and binary64 addition commutes).
+__device__ __forceinline__ double znorm_wave_sum(double v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
+  return v;
+}
+
+// Long chunk c (0-based among all long chunks): its series descriptor and
+// the chunk's place in the series.
+__device__ __forceinline__ ZChunk znorm_long_chunk(const ZDirect& p, int c, int* lg_index) {
+  int j = 0;
+  while (j + 1 < p.nlong && c >= p.lg[j + 1].c0) ++j;
+  *lg_index = j;
+  const ZLong L = p.lg[j];
+  ZChunk q;
+  q.b = L.b;
+  q.n = L.n;
+  q.c0 = L.c0;
+  q.nch = L.nch;
+  q.k = c - L.c0;
+  q.start = L.off + (int64_t)q.k * kZChunk;
+  q.m = min(kZChunk, q.n - q.k * kZChunk);
+  return q;
+}
+
+__device__ __forceinline__ void znorm_chunk_load(const float* x, const ZChunk& q,
+                                                 float (&v)[kZPer]) {
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    const int i = threadIdx.x + u * kZThreads;
+    v[u] = i < q.m ? x[q.start + i] : 0.0f;
+  }
+}
+
+// Short series: one wave each; long-series chunks: their partials.
+__global__ __launch_bounds__(kZThreads) void sdtw_znorm_direct_kernel(const ZDirect p) {
+  __shared__ double red[kZThreads / kWave];
+  if ((int)blockIdx.x >= p.short_wgs) {
+    int j;
+    const ZChunk q = znorm_long_chunk(p, (int)blockIdx.x - p.short_wgs, &j);
+    float v[kZPer];
+    znorm_chunk_load(p.x, q, v);
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kZPer; ++u) s += (double)v[u];   // padding adds +0
+    const double s1 = znorm_block_sum(s, red);
+    const double mk = s1 / q.m;
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < kZPer; ++u) {
+      if (threadIdx.x + u * kZThreads < q.m) {
+        const double d = (double)v[u] - mk;
+        t += d * d;
+      }
+    }
+    const double m2 = znorm_block_sum(t, red);
+    if (threadIdx.x == 0) {
+      const int64_t c = (int64_t)blockIdx.x - p.short_wgs;
+      p.part[2 * c] = s1;
+      p.part[2 * c + 1] = m2;
+    }
+    return;
+  }
+  // where this workgroup's first series starts: the lengths before it
+  __shared__ unsigned long long s_pre;
+  const int first = (int)blockIdx.x * kZSeriesPerWG;
+  if (threadIdx.x == 0) s_pre = 0;
+  __syncthreads();
+  unsigned long long acc = 0;
+  for (int k = threadIdx.x; k < first; k += kZThreads) acc += (unsigned long long)p.lens[k];
+  atomicAdd(&s_pre, acc);
+  __syncthreads();
+  const int wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int b = first + wv;
+  if (b >= p.batch) return;                     // no barrier below
+  int64_t off = (int64_t)s_pre;
+  for (int k = first; k < b; ++k) off += p.lens[k];
+  const int n = p.lens[b];
+  if (n > kZWaveMax) return;                    // a long series: its chunks are elsewhere
+  const int nu = (n + kWave - 1) / kWave;       // loads per lane (uniform)
+  const float* __restrict__ x = p.x + off;
+  float v[kZWavePer];
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) {
+    const int i = lane + u * kWave;
+    v[u] = (u < nu && i < n) ? x[i] : 0.0f;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) s += (double)v[u];   // padding adds +0
+  const double mean = znorm_wave_sum(s) / n;
+  double t = 0.0;
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) {
+    if (lane + u * kWave < n) {
+      const double d = (double)v[u] - mean;
+      t += d * d;
+    }
+  }
+  const double sd = __builtin_sqrt(znorm_wave_sum(t) / n);
+  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
+  float* __restrict__ z = p.z + off;
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) {
+    const int i = lane + u * kWave;
+    if (u < nu && i < n) z[i] = (float)(((double)v[u] - mean) * inv);
+  }
+}
+
+// Long series: combine the chunk partials (fixed order), standardise the
+// chunk.  Grid: one workgroup per long chunk.
+__global__ __launch_bounds__(kZThreads) void sdtw_znorm_long_apply_kernel(const ZDirect p) {
+  __shared__ double red[kZThreads / kWave];
+  int j;
+  const ZChunk q = znorm_long_chunk(p, (int)blockIdx.x, &j);
+  double s = 0.0;
+  for (int k = threadIdx.x; k < q.nch; k += kZThreads) s += p.part[2 * (q.c0 + k)];
+  const double mean = znorm_block_sum(s, red) / q.n;
+  double t = 0.0;
+  for (int k = threadIdx.x; k < q.nch; k += kZThreads) {
+    const int mk_n = min(kZChunk, q.n - k * kZChunk);
+    const double d = p.part[2 * (q.c0 + k)] / mk_n - mean;
+    t += p.part[2 * (q.c0 + k) + 1] + mk_n * (d * d);
+  }
+  const double sd = __builtin_sqrt(znorm_block_sum(t, red) / q.n);
+  float v[kZPer];
+  znorm_chunk_load(p.x, q, v);
+  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
+#pragma unroll
+  for (int u = 0; u < kZPer; ++u) {
+    const int i = threadIdx.x + u * kZThreads;
+    if (i < q.m) p.z[q.start + i] = (float)(((double)v[u] - mean) * inv);
+  }
 }
 
 }  // namespace sdtw

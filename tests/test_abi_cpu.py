@@ -347,3 +347,14 @@ def test_binding_checks_sizes_before_any_call():
     raises(lambda: P.sdtw_znorm(q, h, l, out=torch.zeros(9)), "out must hold exactly 8")
     # right sizes: the remaining complaint is the device
     raises(lambda: P.sdtw_forward(q, h, l, r), "must be a CUDA tensor")
+
+
+def test_hip_failure_reported_without_a_device(L):
+    """With valid arguments but no usable GPU, the launch fails and the call
+    returns SDTW_ERR_HIP (every pointer is a placeholder that only a kernel
+    would dereference, so this runs only where no GPU is visible)."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible: the placeholder pointers must not reach a kernel")
+    rc = _fwd(L, [3, 4], ref_len=100, ws_bytes=1 << 20)
+    assert rc == L.SDTW_ERR_HIP, L.status_string(rc)

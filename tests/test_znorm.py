@@ -94,3 +94,23 @@ def test_znorm_many_long_series():
     want = Z.znorm_f32(x, lens)
     got = _run(x, lens)
     _check(got, want, "300 long series")
+
+
+@pytest.mark.parametrize("nlong", [32, 33])
+def test_znorm_long_series_listed_in_arguments(nlong):
+    """Up to 32 series longer than one wavefront's 4,096 samples are listed in
+    the kernel arguments (two launches, no offset table); a 33rd sends the
+    batch to the offset-table form.  Both must agree with the oracle."""
+    rng = np.random.default_rng(nlong)
+    lens = list(rng.integers(1, 4097, 200))
+    for k in range(nlong):
+        lens.insert(int(rng.integers(0, len(lens) + 1)), int(rng.integers(4097, 20000)))
+    x = workloads.raw_series(lens, seed=nlong + 1)
+    _check(_run(x, lens), Z.znorm_f32(x, lens), f"{nlong} long series")
+
+
+def test_znorm_batch_beyond_direct_form():
+    """More than 16,384 series: the offset-table form."""
+    lens = list(np.random.default_rng(5).integers(1, 300, 17000))
+    x = workloads.raw_series(lens, seed=17)
+    _check(_run(x, lens), Z.znorm_f32(x, lens), "17,000 series")
