@@ -155,6 +155,41 @@ SDTW_API int sdtw_forward(const float *queries, const int32_t *h_query_lens,
                  float *ckpt, int32_t ckpt_every, int32_t variant, int32_t flags,
                  void *workspace, size_t workspace_bytes, void *stream);
 
+/* Size of the device array behind sdtw_forward_noalloc (16 MiB per GPU). */
+#define SDTW_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+
+/*
+ * sdtw_forward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, validation, results and status codes as sdtw_forward,
+ * without the workspace: the call uses a fixed device array of
+ * SDTW_NOALLOC_SCRATCH_BYTES inside the library instead, and allocates and
+ * frees nothing.  Each GPU the library runs on holds its own array until the
+ * process ends.
+ *
+ *   - A batch whose sdtw_forward_workspace_bytes(..., flags, variant)
+ *     exceeds SDTW_NOALLOC_SCRATCH_BYTES is rejected with SDTW_ERR_WORKSPACE
+ *     before anything is enqueued.  That covers any batch of up to about a
+ *     million queries that fit in one row pass of the tile, plus
+ *     SDTW_NOALLOC_SCRATCH_BYTES / (4 * ref_len) row-buffer slots for
+ *     longer queries (sdtw_forward_workspace_bytes describes the slots).
+ *   - The first call on a device looks the array's device address up once
+ *     (hipGetSymbolAddress, with that device current; SDTW_ERR_HIP if that
+ *     fails); make that first call outside a graph capture.
+ *   - All calls on one GPU share that GPU's array, which keeps the last
+ *     call's contents (nothing in it needs to start at zero: the persistent
+ *     form's work counter is reset by a kernel of the same call).  Calls
+ *     that overlap in time on one GPU -- on different streams, or from
+ *     different host threads -- race and give undefined results; serialise
+ *     them, for example on one stream.
+ */
+SDTW_API int sdtw_forward_noalloc(const float *queries, const int32_t *h_query_lens,
+                                  const int32_t *query_lens, int32_t batch,
+                                  const float *reference, int64_t ref_len, int32_t cost_kind,
+                                  float *cost, int64_t *end_pos,
+                                  float *ckpt, int32_t ckpt_every, int32_t variant,
+                                  int32_t flags, void *stream);
+
 /*
  * Bytes of device workspace sdtw_forward_u8 needs: sdtw_forward's (no flags),
  * one byte per query and reference element for the codes, and the codebook.

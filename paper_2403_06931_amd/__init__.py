@@ -11,7 +11,8 @@ from .api import (SDTW_COST_ABSOLUTE, SDTW_COST_SQUARED, SDTW_F_CHECKPOINT,  # n
                   SDTW_F_PERSISTENT, SdtwError, sdtw_align, sdtw_align_workspace_bytes,
                   sdtw_backward, sdtw_backward_workspace_bytes,
                   sdtw_checkpoint_floats, sdtw_default_variant, sdtw_forward,
-                  sdtw_forward_f16, sdtw_forward_f16_workspace_bytes, sdtw_forward_pruned,
+                  sdtw_forward_f16, sdtw_forward_f16_workspace_bytes, sdtw_forward_noalloc,
+                  sdtw_forward_pruned,
                   sdtw_forward_u8, sdtw_forward_u8_workspace_bytes,
                   sdtw_forward_workspace_bytes, sdtw_variant_count, sdtw_variant_info,
                   sdtw_workspace_bytes, sdtw_znorm, sdtw_znorm_workspace_bytes, workspace)

@@ -22,6 +22,7 @@ SDTW_ERR_HIP = -4
 SDTW_F_CHECKPOINT = 1
 SDTW_F_PERSISTENT = 2
 SDTW_MAX_REF_LEN = 1 << 30
+SDTW_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p
@@ -60,6 +61,10 @@ def _load():
                                  ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, _vp, ctypes.c_size_t, _vp]
     lib.sdtw_forward.restype = ctypes.c_int
+    lib.sdtw_forward_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
+                                         ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.c_int32, _vp]
+    lib.sdtw_forward_noalloc.restype = ctypes.c_int
     lib.sdtw_forward_pruned.argtypes = [_vp, _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64,
                                         ctypes.c_float, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                         _vp, ctypes.c_size_t, _vp]

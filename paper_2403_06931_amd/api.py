@@ -223,6 +223,33 @@ def sdtw_forward(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
     return cost, end_pos
 
 
+def sdtw_forward_noalloc(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
+                         reference: torch.Tensor, cost_kind: int = SDTW_COST_SQUARED, *,
+                         cost: torch.Tensor, end_pos: torch.Tensor,
+                         ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
+                         variant: int = -1, flags: int = 0,
+                         stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """sdtw_forward without a workspace (the library's fixed per-GPU array
+    serves instead) and without allocations: the caller passes the outputs.
+    A batch whose workspace would exceed SDTW_NOALLOC_SCRATCH_BYTES raises
+    SdtwError (SDTW_ERR_WORKSPACE).  Calls that overlap on one GPU race."""
+    h = _host_lens(h_query_lens)
+    _check_batch(h, queries, query_lens, reference)
+    b = h.size
+    _check("cost", cost, torch.float32, at_least=b)
+    _check("end_pos", end_pos, torch.int64, at_least=b)
+    _ckpt_arg(h, reference.numel(), ckpt, ckpt_every, bool(flags & SDTW_F_CHECKPOINT))
+    _on_gpu(queries=queries, query_lens=query_lens, reference=reference, cost=cost,
+            end_pos=end_pos, ckpt=ckpt)
+    _check_lens_match(h, query_lens, "query_lens")
+    st = _lib.lib.sdtw_forward_noalloc(
+        _dp(queries), _hp(h), _dp(query_lens), b, _dp(reference), reference.numel(),
+        int(cost_kind), _dp(cost), _dp(end_pos), _dp(ckpt), int(ckpt_every), int(variant),
+        int(flags), _stream(stream))
+    check(st, "sdtw_forward_noalloc")
+    return cost, end_pos
+
+
 def sdtw_forward_pruned(queries: torch.Tensor, h_query_lens, query_lens: torch.Tensor,
                         reference: torch.Tensor, prune_tau: float, *,
                         cost: Optional[torch.Tensor] = None,

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "sdtw.h"
@@ -19,6 +20,13 @@
 
 #include "sdtw_variants.inc"
 SDTW_VARIANTS(SDTW_DECLARE_VARIANT)
+
+// Workspace of the allocation-free forward (sdtw_forward_noalloc): a fixed
+// array of the library's device code.  Every GPU that loads the library
+// holds its own copy, at its own address, until the process ends.  In host
+// code this name is only a handle for hipGetSymbolAddress: kernels and copies
+// take the device address that call returns (scratch_address()).
+static __device__ __align__(256) unsigned char scratch[SDTW_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -191,6 +199,24 @@ int device_cus() {
     v = 256;
   if (dev >= 0 && dev < kMaxDevices) cached[dev] = v;
   return v;
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current; nullptr if the lookup fails.
+void* scratch_address() {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {nullptr};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (addr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr)
+      return nullptr;
+    addr[dev] = p;
+  }
+  return addr[dev];
 }
 
 int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t flags, int cus) {
@@ -445,15 +471,17 @@ namespace {
 int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_t* query_lens,
                  int32_t batch, const float* reference, int64_t ref_len, int cost_kind, float tau,
                  float* cost, int64_t* end_pos, float* ckpt, int32_t ckpt_every, int32_t variant_id,
-                 int32_t flags, void* workspace, size_t workspace_bytes, void* stream_ptr) {
+                 int32_t flags, void* workspace, size_t workspace_bytes, void* stream_ptr,
+                 bool use_scratch = false) {
   int64_t total = 0;
   int32_t nmax = 0;
-  if (!queries || !query_lens || !reference || !cost || !end_pos || !workspace)
+  if (!queries || !query_lens || !reference || !cost || !end_pos || (!workspace && !use_scratch))
     return SDTW_ERR_INVALID_ARG;
   if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
     return SDTW_ERR_INVALID_ARG;
   if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return SDTW_ERR_INVALID_ARG;
-  if ((reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return SDTW_ERR_INVALID_ARG;
+  if (!use_scratch && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
+    return SDTW_ERR_INVALID_ARG;
   const bool want_ckpt = (flags & SDTW_F_CHECKPOINT) != 0;
   int64_t nck = 0;
   if (want_ckpt) {
@@ -471,7 +499,15 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
   const int64_t slots = cost_kind == kU8Codes ? batch
                                               : fwd_slots(v, h_query_lens, batch, flags, cus);
   const FwdLayout L = fwd_layout(batch, ref_len, flags, slots);
-  if (workspace_bytes < L.total) return SDTW_ERR_WORKSPACE;
+  if (use_scratch) {
+    // the library's own array (256-byte aligned), checked against its size
+    // before any HIP call
+    if (L.total > SDTW_NOALLOC_SCRATCH_BYTES) return SDTW_ERR_WORKSPACE;
+    workspace = scratch_address();
+    if (workspace == nullptr) return SDTW_ERR_HIP;
+  } else if (workspace_bytes < L.total) {
+    return SDTW_ERR_WORKSPACE;
+  }
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   char* ws = static_cast<char*>(workspace);
 
@@ -546,6 +582,18 @@ int sdtw_forward(const float* queries, const int32_t* h_query_lens, const int32_
   return forward_impl(queries, h_query_lens, query_lens, batch, reference, ref_len, cost_kind,
                       0.0f, cost, end_pos, ckpt, ckpt_every, variant_id, flags, workspace,
                       workspace_bytes, stream_ptr);
+}
+
+int sdtw_forward_noalloc(const float* queries, const int32_t* h_query_lens,
+                         const int32_t* query_lens, int32_t batch, const float* reference,
+                         int64_t ref_len, int32_t cost_kind, float* cost, int64_t* end_pos,
+                         float* ckpt, int32_t ckpt_every, int32_t variant_id, int32_t flags,
+                         void* stream_ptr) {
+  if (cost_kind != SDTW_COST_SQUARED && cost_kind != SDTW_COST_ABSOLUTE)
+    return SDTW_ERR_INVALID_ARG;
+  return forward_impl(queries, h_query_lens, query_lens, batch, reference, ref_len, cost_kind,
+                      0.0f, cost, end_pos, ckpt, ckpt_every, variant_id, flags, nullptr, 0,
+                      stream_ptr, true);
 }
 
 int sdtw_forward_pruned(const float* queries, const int32_t* h_query_lens,

@@ -358,3 +358,39 @@ def test_hip_failure_reported_without_a_device(L):
         pytest.skip("a GPU is visible: the placeholder pointers must not reach a kernel")
     rc = _fwd(L, [3, 4], ref_len=100, ws_bytes=1 << 20)
     assert rc == L.SDTW_ERR_HIP, L.status_string(rc)
+
+
+def _fwd_noalloc(L, lens, ref_len=100, kind=0, flags=0, q=FAKE, r=FAKE, c=FAKE, e=FAKE,
+                 ckpt=0, every=0, variant=-1, dlens=FAKE):
+    h = np.ascontiguousarray(lens, dtype=np.int32)
+    return L.lib.sdtw_forward_noalloc(_vp(q), _vp(h.ctypes.data if h.size else 0), _vp(dlens),
+                                      h.size, _vp(r), ref_len, kind, _vp(c), _vp(e), _vp(ckpt),
+                                      every, variant, flags, _vp(0))
+
+
+def test_forward_noalloc_validation(L):
+    """The allocation-free forward validates like sdtw_forward and refuses,
+    before any HIP call, a batch whose workspace exceeds its fixed array."""
+    E = L.SDTW_ERR_INVALID_ARG
+    assert _fwd_noalloc(L, [3, 4], q=0) == E
+    assert _fwd_noalloc(L, [3, 4], c=0) == E
+    assert _fwd_noalloc(L, [3, 0]) == E
+    assert _fwd_noalloc(L, [3, 4], kind=2) == E
+    assert _fwd_noalloc(L, [3, 4], flags=4) == E
+    assert _fwd_noalloc(L, [3, 4], flags=1, every=24) == E       # not a multiple of 16
+    assert _fwd_noalloc(L, [3, 4], variant=10**6) == L.SDTW_ERR_UNSUPPORTED
+    import paper_2403_06931_amd as P
+    big = _variant_of((8, 8, 4, 32, 1))
+    lens = np.full(40, 5000, np.int32)       # 40 row-buffer slots of 800 KB
+    assert P.sdtw_forward_workspace_bytes(lens, 200_000, 0, big) > L.SDTW_NOALLOC_SCRATCH_BYTES
+    assert _fwd_noalloc(L, lens, ref_len=200_000, variant=big) == L.SDTW_ERR_WORKSPACE
+
+
+def test_forward_noalloc_without_a_device(L):
+    """Valid arguments but no GPU: the array's address cannot be looked up
+    and the call returns SDTW_ERR_HIP."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible: the placeholder pointers must not reach a kernel")
+    rc = _fwd_noalloc(L, [3, 4], ref_len=100)
+    assert rc == L.SDTW_ERR_HIP, L.status_string(rc)
