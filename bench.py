@@ -236,12 +236,18 @@ def batched_leg(P, torch, steps, warmup, oracle_legs=True):
     q = torch.from_numpy(w.queries).to(dev)
     l = torch.from_numpy(w.lens).to(dev)
     r = torch.from_numpy(w.reference).to(dev)
-    flags = P.SDTW_F_PERSISTENT
-    rec = {}
+    rec, rec_grid = {}, {}
     # persistent candidates: at most four wavefronts per query (wider teams
-    # waste most of their lanes on the short queries of this batch)
+    # waste most of their lanes on the short queries of this batch), timed
+    # with the default grid; then the four fastest with grids of 2, 3 and 4
+    # resident wavefronts per SIMD
     cands = [v for v in range(P.sdtw_variant_count()) if P.sdtw_variant_info(v)[2] <= 4]
-    variant = P.autotune.tune(q, w.lens, l, r, 0, flags, candidates=cands, reps=1, record=rec)
+    P.autotune.tune(q, w.lens, l, r, 0, P.SDTW_F_PERSISTENT, candidates=cands, reps=1,
+                    record=rec)
+    top = sorted(rec["times_ms"], key=rec["times_ms"].get)[:4]
+    variant, flags = P.autotune.tune_persistent(q, w.lens, l, r, 0, candidates=top,
+                                                waves_per_simd=(2, 3, 4), reps=1,
+                                                record=rec_grid)
     # the timed step is the captured launch sequence (order + work-counter
     # reset, persistent kernel), replayed
     g = P.ForwardGraph(q, w.lens, l, r, 0, flags=flags, variant=variant)
@@ -272,7 +278,9 @@ def batched_leg(P, torch, steps, warmup, oracle_legs=True):
                for idx, _, _, _, _, cb, _ in buckets)
     del g, buckets
     out = {"workload": w.name, "digest": workloads.digest(w), "cells": w.cells,
-           "variant": P.sdtw_variant_info(variant), "tuned_over": len(rec.get("times_ms", {})),
+           "variant": P.sdtw_variant_info(variant), "waves_per_simd": (flags >> 8) & 0xf,
+           "tuned_over": len(rec.get("times_ms", {})) + len(rec_grid.get("times_ms", {})),
+           "grid_times_ms": rec_grid.get("times_ms"),
            "timed": "ForwardGraph.replay() (hipGraph of the persistent launch)",
            "gcups": w.cells / (ev_ms * 1e6), "ms_per_step": ev_ms,
            "gsps": float(w.lens.sum()) / (ev_ms * 1e6),
@@ -546,7 +554,11 @@ def u8_leg(P, torch, exact_cost, exact_end, steps, warmup):
 
 
 def znorm_leg(P, torch, steps, warmup):
-    """sdtw_znorm on raw (unnormalised) series of the evaluation's shapes."""
+    """sdtw_znorm on raw (unnormalised) series of the evaluation's shapes.
+    A call takes microseconds, less than the host needs to enqueue it, so
+    back-to-back eager calls measure the host; the GPU time per call is taken
+    from one HIP graph holding `steps` calls, replayed between events (the
+    eager time per call is reported beside it)."""
     import numpy as np
 
     import workloads
@@ -568,8 +580,26 @@ def znorm_leg(P, torch, steps, warmup):
         def run():
             P.sdtw_znorm(x, h, lt, out=z, workspace_buf=wsb)
         wall_ms, ev_ms = time_steps(run, steps, warmup, torch)
-        gbs = 8.0 * x.numel() / (ev_ms * 1e6)
-        out[name] = {"samples": int(x.numel()), "ms": ev_ms, "wall_ms": wall_ms,
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(steps):
+                run()
+        graph.replay()
+        torch.cuda.synchronize()
+        reps = 5
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        g_ms = e0.elapsed_time(e1) / (reps * steps)
+        del graph
+        gbs = 8.0 * x.numel() / (g_ms * 1e6)
+        out[name] = {"samples": int(x.numel()), "ms": g_ms, "timed": "HIP graph of back-to-back calls",
+                     "eager_ms": ev_ms, "eager_wall_ms": wall_ms,
                      "GB/s": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
     return {"bound": "hbm", "peak_GB/s": HBM_PEAK_GBS,
             "bytes_per_sample": 8, "sets": out}
@@ -589,6 +619,8 @@ def main():
                     help="only time the batch z-normaliser (sdtw_znorm) and exit")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the library's built-in variant choice instead of timing all variants")
+    ap.add_argument("--leg-only", choices=("batched", "fwd_bwd", "long_ref", "f16"),
+                    help="time only this leg (no headline, no oracle) and print its record")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -610,6 +642,19 @@ def main():
     if args.u8_only:
         print(json.dumps({"u8": u8_leg(P, torch, None, None, steps=args.steps,
                                        warmup=args.warmup)}), flush=True)
+        return
+    if args.leg_only:
+        if args.leg_only == "long_ref":
+            w1 = workloads.make_config(1)
+            v = args.variant if args.variant >= 0 else P.sdtw_default_variant(w1.lens, w1.ref_len)
+            rec = long_ref_leg(P, torch, v, steps=args.steps, warmup=args.warmup,
+                               oracle_legs=False)
+        elif args.leg_only == "f16":
+            rec = f16_leg(P, torch, steps=args.steps, warmup=args.warmup)
+        else:
+            fn = batched_leg if args.leg_only == "batched" else fwd_bwd_leg
+            rec = fn(P, torch, steps=args.steps, warmup=args.warmup, oracle_legs=False)
+        print(json.dumps({args.leg_only: rec}), flush=True)
         return
 
     dev = torch.device("cuda:0")

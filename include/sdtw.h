@@ -79,6 +79,16 @@ enum {
     SDTW_F_PERSISTENT = 2
 };
 
+/* Size of the persistent grid, in flags bits 8..11: SDTW_F_WAVES_PER_SIMD(n)
+ * asks for n resident wavefronts per SIMD (n = 1..8; 0 or absent: 2), i.e. a
+ * grid of min(batch, CUs * 4 * n / W) workgroups of W wavefronts.  Ignored
+ * without SDTW_F_PERSISTENT.  The grid size changes the workspace (one
+ * row-buffer slot per workgroup when a query needs several passes), never
+ * the results. */
+#define SDTW_F_WAVES_SHIFT 8
+#define SDTW_F_WAVES_MASK (0xf << SDTW_F_WAVES_SHIFT)
+#define SDTW_F_WAVES_PER_SIMD(n) ((int32_t)(n) << SDTW_F_WAVES_SHIFT)
+
 /* Largest accepted reference length (column indices are 32-bit inside the
  * kernels). */
 #define SDTW_MAX_REF_LEN ((int64_t)1 << 30)

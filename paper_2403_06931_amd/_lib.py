@@ -21,6 +21,14 @@ SDTW_ERR_UNSUPPORTED = -3
 SDTW_ERR_HIP = -4
 SDTW_F_CHECKPOINT = 1
 SDTW_F_PERSISTENT = 2
+SDTW_F_WAVES_SHIFT = 8
+
+
+def SDTW_F_WAVES_PER_SIMD(n: int) -> int:
+    """Flags bits asking the persistent grid for n resident wavefronts per SIMD."""
+    return int(n) << SDTW_F_WAVES_SHIFT
+
+
 SDTW_MAX_REF_LEN = 1 << 30
 SDTW_NOALLOC_SCRATCH_BYTES = 16 << 20
 

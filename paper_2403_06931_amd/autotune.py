@@ -20,7 +20,7 @@ from __future__ import annotations
 import json
 import os
 import statistics
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -113,6 +113,33 @@ def tune(queries, h_lens, query_lens, reference, cost_kind: int = 0, flags: int 
     best = min(results, key=results.get)
     if record is not None:
         record.update({"times_ms": results, "best": best})
+    return best
+
+
+def tune_persistent(queries, h_lens, query_lens, reference, cost_kind: int = 0,
+                    flags: int = api.SDTW_F_PERSISTENT,
+                    candidates: Optional[Sequence[int]] = None,
+                    waves_per_simd: Sequence[int] = (2, 3, 4), reps: int = 3,
+                    record: Optional[dict] = None) -> Tuple[int, int]:
+    """Time every (variant, grid size) pair of the persistent launch on this
+    batch: the grid holds waves_per_simd resident wavefronts per SIMD
+    (SDTW_F_WAVES_PER_SIMD).  Returns the fastest (variant, flags)."""
+    h = api._host_lens(h_lens)
+    if candidates is None:
+        candidates = range(api.sdtw_variant_count())
+    base = (int(flags) | api.SDTW_F_PERSISTENT) & ~(0xf << 8)
+    pairs = [(int(v), base | api.SDTW_F_WAVES_PER_SIMD(w)) for v in candidates
+             for w in waves_per_simd]
+    ws = api.workspace(max(api.sdtw_forward_workspace_bytes(h, reference.numel(), f, v)
+                           for v, f in pairs), queries.device)
+    results = {}
+    for v, f in pairs:
+        results[(v, f)] = time_variant(v, queries, h, query_lens, reference, cost_kind, f,
+                                       reps=reps, workspace_buf=ws)
+    best = min(results, key=results.get)
+    if record is not None:
+        record.update({"times_ms": {f"{v}/{f >> 8}": t for (v, f), t in results.items()},
+                       "best": best})
     return best
 
 

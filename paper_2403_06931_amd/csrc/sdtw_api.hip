@@ -129,10 +129,20 @@ U8Layout u8_layout(int32_t batch, int64_t total_rows, int64_t ref_len) {
 
 constexpr int kU8Codes = 3;             // forward_impl's kind for the code DP
 
-// Persistent grid: eight waves per CU (two per SIMD), at most one workgroup
-// per query.
-int64_t persistent_grid_for(const Variant& v, int32_t batch, int cus) {
-  return std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)cus * 8 / v.W));
+// Forward flags: checkpoints, persistent launch and the persistent grid's
+// wavefronts per SIMD (0 = the default, 2; at most 8).
+constexpr int32_t kFwdFlags = SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT | SDTW_F_WAVES_MASK;
+
+bool fwd_flags_ok(int32_t flags) {
+  return (flags & ~kFwdFlags) == 0 && ((flags & SDTW_F_WAVES_MASK) >> SDTW_F_WAVES_SHIFT) <= 8;
+}
+
+// Persistent grid: the requested wavefronts per SIMD (default two), at most
+// one workgroup per query.
+int64_t persistent_grid_for(const Variant& v, int32_t batch, int cus, int32_t flags) {
+  const int wps = (flags & SDTW_F_WAVES_MASK) >> SDTW_F_WAVES_SHIFT;
+  const int64_t waves_per_cu = 4LL * (wps > 0 ? wps : 2);
+  return std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)cus * waves_per_cu / v.W));
 }
 
 // Row-buffer slots a forward launch of variant v needs: the plain launch
@@ -145,7 +155,7 @@ int64_t fwd_slots(const Variant& v, const int32_t* h_lens, int32_t batch, int32_
   const int64_t rows = 64LL * v.R * v.W;
   int64_t multi = 0;
   for (int32_t b = 0; b < batch; ++b) multi += h_lens[b] > rows ? 1 : 0;
-  if (flags & SDTW_F_PERSISTENT) return multi > 0 ? persistent_grid_for(v, batch, cus) : 0;
+  if (flags & SDTW_F_PERSISTENT) return multi > 0 ? persistent_grid_for(v, batch, cus, flags) : 0;
   return multi;
 }
 
@@ -444,7 +454,7 @@ int32_t sdtw_default_variant(const int32_t* h_query_lens, int32_t batch, int64_t
 size_t sdtw_forward_workspace_bytes(const int32_t* h_query_lens, int32_t batch, int64_t ref_len,
                                     int32_t flags, int32_t variant_id) {
   if (!lens_ok(h_query_lens, batch, nullptr, nullptr) || !ref_ok(ref_len)) return 0;
-  if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return 0;
+  if (!fwd_flags_ok(flags)) return 0;
   if (variant_id < -1 || variant_id >= variant_count()) return 0;
   const int cus = device_cus();
   const int vid = variant_id >= 0 ? variant_id
@@ -479,7 +489,7 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
     return SDTW_ERR_INVALID_ARG;
   if (!lens_ok(h_query_lens, batch, &total, &nmax) || !ref_ok(ref_len))
     return SDTW_ERR_INVALID_ARG;
-  if (flags & ~(SDTW_F_CHECKPOINT | SDTW_F_PERSISTENT)) return SDTW_ERR_INVALID_ARG;
+  if (!fwd_flags_ok(flags)) return SDTW_ERR_INVALID_ARG;
   if (!use_scratch && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0)
     return SDTW_ERR_INVALID_ARG;
   const bool want_ckpt = (flags & SDTW_F_CHECKPOINT) != 0;
@@ -559,7 +569,7 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
     int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_order_kernel), dim3(1),
                     dim3(sdtw::kScanThreads), oargs, stream);
     if (rc != SDTW_OK) return rc;
-    const int grid = (int)persistent_grid_for(v, batch, cus);
+    const int grid = (int)persistent_grid_for(v, batch, cus, flags);
     void* args[] = {(void*)&p};
     return launch(pruned ? v.pruned[1] : v.persistent[cost_kind][ck], dim3(grid),
                   dim3(64 * v.W), args, stream);
@@ -602,7 +612,7 @@ int sdtw_forward_pruned(const float* queries, const int32_t* h_query_lens,
                         int32_t variant_id, int32_t flags, void* workspace,
                         size_t workspace_bytes, void* stream_ptr) {
   if (prune_tau != prune_tau) return SDTW_ERR_INVALID_ARG;          // NaN
-  if (flags & ~SDTW_F_PERSISTENT) return SDTW_ERR_INVALID_ARG;      // no checkpoints
+  if (flags & SDTW_F_CHECKPOINT) return SDTW_ERR_INVALID_ARG;       // no checkpoints
   return forward_impl(queries, h_query_lens, query_lens, batch, reference, ref_len,
                       sdtw::kPruned, prune_tau, cost, end_pos, nullptr, 0, variant_id, flags,
                       workspace, workspace_bytes, stream_ptr);
@@ -867,12 +877,15 @@ int sdtw_znorm(const float* x, const int32_t* h_lens, const int32_t* lens, int32
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   char* ws = static_cast<char*>(workspace);
   if (batch <= sdtw::kZDirectBatch) {
-    // direct form: the host lists the long series (it knows their offsets)
+    // direct form: the host lists the long series and every stride-th
+    // series' first element (it knows both from the host lengths)
     sdtw::ZDirect d{};
+    d.stride = (batch + sdtw::kZCoarse - 1) / sdtw::kZCoarse;
     int64_t off = 0;
     int32_t long_chunks = 0;
     bool fits = true;
     for (int32_t b = 0; b < batch && fits; ++b) {
+      if (b % d.stride == 0) d.prefix[b / d.stride] = off;
       if (h_lens[b] > sdtw::kZWaveMax) {
         if (d.nlong == sdtw::kZMaxLong) {
           fits = false;
@@ -891,14 +904,16 @@ int sdtw_znorm(const float* x, const int32_t* h_lens, const int32_t* lens, int32
       d.lens = lens;
       d.part = reinterpret_cast<double*>(ws + L.part);
       d.batch = batch;
-      d.short_wgs = (batch + sdtw::kZSeriesPerWG - 1) / sdtw::kZSeriesPerWG;
+      d.long_chunks = long_chunks;
       void* args[] = {(void*)&d};
+      constexpr int wpg = sdtw::kZWavesPerWG;
       int rc = launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_direct_kernel),
-                      dim3((unsigned)(d.short_wgs + long_chunks)), dim3(sdtw::kZThreads), args,
-                      stream);
+                      dim3((unsigned)((batch + long_chunks + wpg - 1) / wpg)),
+                      dim3(sdtw::kZThreads), args, stream);
       if (rc != SDTW_OK || long_chunks == 0) return rc;
       return launch(reinterpret_cast<const void*>(&sdtw::sdtw_znorm_long_apply_kernel),
-                    dim3((unsigned)long_chunks), dim3(sdtw::kZThreads), args, stream);
+                    dim3((unsigned)((long_chunks + wpg - 1) / wpg)), dim3(sdtw::kZThreads),
+                    args, stream);
     }
   }
   // table form

@@ -13,15 +13,16 @@
 // Direct form (batches of up to kZDirectBatch series with at most kZMaxLong
 // series longer than kZWaveMax):
 //   * one launch standardises every short series (up to kZWaveMax samples)
-//     with one wavefront each, the series held in registers (up to 64 per
-//     lane, loads coalesced across the wavefront) and both sums reduced by a
-//     butterfly within the wavefront: no barrier and no LDS.  A workgroup
-//     takes kZSeriesPerWG consecutive series and finds where they start by
-//     summing the lengths before them (a few kilobytes from L2), so no
-//     offset table and no extra launch is needed.  Workgroups past those
-//     take the chunks of the long series, which the host describes in the
-//     kernel arguments (it knows their offsets from the host lengths), and
-//     store each chunk's sum and sum of squared deviations;
+//     with one wavefront each, the series held in registers (64 samples per
+//     lane), both sums reduced within the wavefront with DPP moves: no
+//     barrier and no LDS.  Loads and stores go through buffer resources
+//     bounded by the series' length, so a lane needs no bounds test.  The
+//     host passes the first element of every stride-th series in the kernel
+//     arguments, so a wavefront finds its series by adding at most
+//     stride - 1 lengths: no offset table and no extra launch.  Wavefronts
+//     past those take the 4096-sample chunks of the long series, which the
+//     host also lists in the arguments, and store each chunk's sum and sum of
+//     squared deviations;
 //   * a second launch, only when there are long series, combines a long
 //     series' chunk partials exactly in a fixed order (sum of squares = sum
 //     over chunks of the chunk's own sum plus n_k (mean_k - mean)^2) and
@@ -227,10 +228,13 @@ __global__ __launch_bounds__(kZThreads) void sdtw_znorm_apply_kernel(const ZPara
 // ------------------------------------------------------------ direct form
 
 constexpr int kZWavePer = 64;                        // samples per lane
-constexpr int kZWaveMax = kWave * kZWavePer;         // series standardised by one wave
-constexpr int kZSeriesPerWG = kZThreads / kWave;     // one wave per series
+constexpr int kZWaveMax = kWave * kZWavePer;         // series standardised by one wavefront
+constexpr int kZWavesPerWG = kZThreads / kWave;
 constexpr int kZMaxLong = 32;                        // long series in the kernel arguments
+constexpr int kZCoarse = 256;                        // prefix entries in the kernel arguments
 constexpr int32_t kZDirectBatch = 16384;
+constexpr int kZMaxStride = kZDirectBatch / kZCoarse;   // series per prefix entry, at most
+static_assert(kZMaxStride <= kWave, "a wavefront sums the lengths after a prefix entry");
 static_assert(kZWaveMax == kZChunk, "a short series is one chunk of the table form");
 
 struct ZLong {
@@ -245,25 +249,115 @@ struct ZDirect {
   const int32_t* lens;
   double* part;                 // [long chunks][2]
   int32_t batch;
-  int32_t short_wgs;            // workgroups of the short series (first in the grid)
-  int32_t nlong;
+  int32_t stride;               // series per prefix entry
+  int32_t nlong;                // long series
+  int32_t long_chunks;          // their chunks
   ZLong lg[kZMaxLong];
+  int64_t prefix[kZCoarse];     // first element of series k * stride
 };
 
-// Sum over the 64 lanes of a wavefront: every lane ends with the same bits
-// (each step adds the same two values, and binary64 addition commutes).
-__device__ __forceinline__ double znorm_wave_sum(double v) {
+// 64-bit wavefront sums with DPP moves (no LDS traffic): pairs within quads,
+// then mirrored half rows and rows of 16 lanes (all lanes of a group hold
+// equal values by then, so a mirror adds the other half's sum), then the
+// four row sums read out and added in row order.  The order is fixed, so the
+// bits are the same on every run; every lane gets the result.
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long u) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffu), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long u, int lane) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+template <typename T, typename Add>
+__device__ __forceinline__ T wave_sum_dpp(T v, Add add) {
+  auto bits = [](T x) { return __builtin_bit_cast(unsigned long long, x); };
+  auto val = [](unsigned long long u) { return __builtin_bit_cast(T, u); };
+  v = add(v, val(dpp_u64<0xb1>(bits(v))));   // quad_perm [1,0,3,2]
+  v = add(v, val(dpp_u64<0x4e>(bits(v))));   // quad_perm [2,3,0,1]
+  v = add(v, val(dpp_u64<0x141>(bits(v))));  // row_half_mirror
+  v = add(v, val(dpp_u64<0x140>(bits(v))));  // row_mirror
+  return add(add(add(val(readlane_u64(bits(v), 0)), val(readlane_u64(bits(v), 16))),
+                 val(readlane_u64(bits(v), 32))),
+             val(readlane_u64(bits(v), 48)));
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  return wave_sum_dpp(v, [](double a, double b) { return a + b; });
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v) {
+  return wave_sum_dpp(v, [](long long a, long long b) { return a + b; });
+}
+
+// A buffer resource over m floats at p: loads past the end read zero and
+// stores past it are dropped, so every lane loads and stores its 64 samples
+// without a branch or a bounds test.  (The raw buffer builtins move 32-bit
+// patterns: values are bit-cast, never converted.)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t znorm_rsrc(const float* p, int m) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, m * 4,
+                                           0x00020000);
+}
+
+// The m (<= kZWaveMax) samples of a series or chunk, 64 per lane (sample
+// lane + 64u in v[u]; zero past the end), all loads in flight together.
+__device__ __forceinline__ void znorm_wave_load(__amdgpu_buffer_rsrc_t src, int lane,
+                                                float (&v)[kZWavePer]) {
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d);
-  return v;
+  for (int u = 0; u < kZWavePer; ++u)
+    v[u] = __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(src, (lane + kWave * u) * 4, 0, 0));
+}
+
+// Keep the samples as binary32 between passes: without this the compiler
+// holds all 64 binary64 conversions live (128 more registers per lane).
+__device__ __forceinline__ void znorm_fence(float (&v)[kZWavePer]) {
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) asm volatile("" : "+v"(v[u]));
+}
+
+// Sum of the m loaded samples and their sum of squared deviations from
+// their mean, over the wavefront (four partial sums per lane, added in a
+// fixed order).
+__device__ __forceinline__ void znorm_wave_moments(float (&v)[kZWavePer], int m, int lane,
+                                                   double& s1, double& m2) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) a[u & 3] += (double)v[u];   // padding adds +0
+  s1 = wave_sum_f64((a[0] + a[1]) + (a[2] + a[3]));
+  znorm_fence(v);
+  const double mk = s1 / m;
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u) {
+    const double d = (double)v[u] - mk;
+    t[u & 3] += lane + kWave * u < m ? d * d : 0.0;
+  }
+  m2 = wave_sum_f64((t[0] + t[1]) + (t[2] + t[3]));
+  znorm_fence(v);
+}
+
+__device__ __forceinline__ void znorm_wave_store(__amdgpu_buffer_rsrc_t dst, int lane,
+                                                 const float (&v)[kZWavePer], double mean,
+                                                 double sd) {
+  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
+#pragma unroll
+  for (int u = 0; u < kZWavePer; ++u)
+    __builtin_amdgcn_raw_buffer_store_b32(
+        __builtin_bit_cast(uint32_t, (float)(((double)v[u] - mean) * inv)), dst,
+        (lane + kWave * u) * 4, 0, 0);
 }
 
 // Long chunk c (0-based among all long chunks): its series descriptor and
 // the chunk's place in the series.
-__device__ __forceinline__ ZChunk znorm_long_chunk(const ZDirect& p, int c, int* lg_index) {
+__device__ __forceinline__ ZChunk znorm_long_chunk(const ZDirect& p, int c) {
   int j = 0;
   while (j + 1 < p.nlong && c >= p.lg[j + 1].c0) ++j;
-  *lg_index = j;
   const ZLong L = p.lg[j];
   ZChunk q;
   q.b = L.b;
@@ -276,115 +370,67 @@ __device__ __forceinline__ ZChunk znorm_long_chunk(const ZDirect& p, int c, int*
   return q;
 }
 
-__device__ __forceinline__ void znorm_chunk_load(const float* x, const ZChunk& q,
-                                                 float (&v)[kZPer]) {
-#pragma unroll
-  for (int u = 0; u < kZPer; ++u) {
-    const int i = threadIdx.x + u * kZThreads;
-    v[u] = i < q.m ? x[q.start + i] : 0.0f;
-  }
-}
-
-// Short series: one wave each; long-series chunks: their partials.
+// One wavefront per item: items [0, batch) are the series (a short one, of
+// at most kZWaveMax samples, is standardised here; a long one's item does
+// nothing), items [batch, batch + long_chunks) the chunks of the long series,
+// which the host lists in the arguments: their sum and sum of squared
+// deviations go to `part`.  A short series' first element is the prefix
+// entry before it (host-given) plus at most stride - 1 lengths.  No barrier
+// and no LDS: every wavefront works alone.
 __global__ __launch_bounds__(kZThreads) void sdtw_znorm_direct_kernel(const ZDirect p) {
-  __shared__ double red[kZThreads / kWave];
-  if ((int)blockIdx.x >= p.short_wgs) {
-    int j;
-    const ZChunk q = znorm_long_chunk(p, (int)blockIdx.x - p.short_wgs, &j);
-    float v[kZPer];
-    znorm_chunk_load(p.x, q, v);
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < kZPer; ++u) s += (double)v[u];   // padding adds +0
-    const double s1 = znorm_block_sum(s, red);
-    const double mk = s1 / q.m;
-    double t = 0.0;
-#pragma unroll
-    for (int u = 0; u < kZPer; ++u) {
-      if (threadIdx.x + u * kZThreads < q.m) {
-        const double d = (double)v[u] - mk;
-        t += d * d;
-      }
-    }
-    const double m2 = znorm_block_sum(t, red);
-    if (threadIdx.x == 0) {
-      const int64_t c = (int64_t)blockIdx.x - p.short_wgs;
-      p.part[2 * c] = s1;
-      p.part[2 * c + 1] = m2;
-    }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int item = (int)blockIdx.x * kZWavesPerWG +
+                   __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  float v[kZWavePer];
+  if (item < p.batch) {
+    const int b = item;
+    const int e0 = (b / p.stride) * p.stride;   // series of the prefix entry
+    const int n = __builtin_amdgcn_readfirstlane(p.lens[b]);
+    const long long mine = lane < b - e0 ? (long long)p.lens[e0 + lane] : 0;
+    if (n > kZWaveMax) return;                  // a long series: its chunks are elsewhere
+    const int64_t off = p.prefix[b / p.stride] + wave_sum_i64(mine);
+    znorm_wave_load(znorm_rsrc(p.x + off, n), lane, v);
+    double s1, m2;
+    znorm_wave_moments(v, n, lane, s1, m2);
+    znorm_wave_store(znorm_rsrc(p.z + off, n), lane, v, s1 / n, __builtin_sqrt(m2 / n));
     return;
   }
-  // where this workgroup's first series starts: the lengths before it
-  __shared__ unsigned long long s_pre;
-  const int first = (int)blockIdx.x * kZSeriesPerWG;
-  if (threadIdx.x == 0) s_pre = 0;
-  __syncthreads();
-  unsigned long long acc = 0;
-  for (int k = threadIdx.x; k < first; k += kZThreads) acc += (unsigned long long)p.lens[k];
-  atomicAdd(&s_pre, acc);
-  __syncthreads();
-  const int wv = threadIdx.x / kWave;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int b = first + wv;
-  if (b >= p.batch) return;                     // no barrier below
-  int64_t off = (int64_t)s_pre;
-  for (int k = first; k < b; ++k) off += p.lens[k];
-  const int n = p.lens[b];
-  if (n > kZWaveMax) return;                    // a long series: its chunks are elsewhere
-  const int nu = (n + kWave - 1) / kWave;       // loads per lane (uniform)
-  const float* __restrict__ x = p.x + off;
-  float v[kZWavePer];
-#pragma unroll
-  for (int u = 0; u < kZWavePer; ++u) {
-    const int i = lane + u * kWave;
-    v[u] = (u < nu && i < n) ? x[i] : 0.0f;
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int u = 0; u < kZWavePer; ++u) s += (double)v[u];   // padding adds +0
-  const double mean = znorm_wave_sum(s) / n;
-  double t = 0.0;
-#pragma unroll
-  for (int u = 0; u < kZWavePer; ++u) {
-    if (lane + u * kWave < n) {
-      const double d = (double)v[u] - mean;
-      t += d * d;
-    }
-  }
-  const double sd = __builtin_sqrt(znorm_wave_sum(t) / n);
-  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
-  float* __restrict__ z = p.z + off;
-#pragma unroll
-  for (int u = 0; u < kZWavePer; ++u) {
-    const int i = lane + u * kWave;
-    if (u < nu && i < n) z[i] = (float)(((double)v[u] - mean) * inv);
+  const int c = item - p.batch;
+  if (c >= p.long_chunks) return;
+  const ZChunk q = znorm_long_chunk(p, c);
+  znorm_wave_load(znorm_rsrc(p.x + q.start, q.m), lane, v);
+  double s1, m2;
+  znorm_wave_moments(v, q.m, lane, s1, m2);
+  if (lane == 0) {
+    p.part[2 * (int64_t)c] = s1;
+    p.part[2 * (int64_t)c + 1] = m2;
   }
 }
 
-// Long series: combine the chunk partials (fixed order), standardise the
-// chunk.  Grid: one workgroup per long chunk.
+// Long series: combine the series' chunk partials (each lane a fixed subset
+// of the chunks in order, then the wavefront sum), then standardise this
+// wavefront's chunk.  One wavefront per long chunk.
 __global__ __launch_bounds__(kZThreads) void sdtw_znorm_long_apply_kernel(const ZDirect p) {
-  __shared__ double red[kZThreads / kWave];
-  int j;
-  const ZChunk q = znorm_long_chunk(p, (int)blockIdx.x, &j);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = (int)blockIdx.x * kZWavesPerWG +
+                __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  if (c >= p.long_chunks) return;
+  const ZChunk q = znorm_long_chunk(p, c);
+  float v[kZWavePer];
+  znorm_wave_load(znorm_rsrc(p.x + q.start, q.m), lane, v);
+  znorm_fence(v);
   double s = 0.0;
-  for (int k = threadIdx.x; k < q.nch; k += kZThreads) s += p.part[2 * (q.c0 + k)];
-  const double mean = znorm_block_sum(s, red) / q.n;
+  for (int k = lane; k < q.nch; k += kWave) s += p.part[2 * (q.c0 + k)];
+  const double mean = wave_sum_f64(s) / q.n;
   double t = 0.0;
-  for (int k = threadIdx.x; k < q.nch; k += kZThreads) {
+  for (int k = lane; k < q.nch; k += kWave) {
     const int mk_n = min(kZChunk, q.n - k * kZChunk);
     const double d = p.part[2 * (q.c0 + k)] / mk_n - mean;
     t += p.part[2 * (q.c0 + k) + 1] + mk_n * (d * d);
   }
-  const double sd = __builtin_sqrt(znorm_block_sum(t, red) / q.n);
-  float v[kZPer];
-  znorm_chunk_load(p.x, q, v);
-  const double inv = sd > 0.0 ? 1.0 / sd : 0.0;
-#pragma unroll
-  for (int u = 0; u < kZPer; ++u) {
-    const int i = threadIdx.x + u * kZThreads;
-    if (i < q.m) p.z[q.start + i] = (float)(((double)v[u] - mean) * inv);
-  }
+  const double sd = __builtin_sqrt(wave_sum_f64(t) / q.n);
+  znorm_fence(v);
+  znorm_wave_store(znorm_rsrc(p.z + q.start, q.m), lane, v, mean, sd);
 }
 
 }  // namespace sdtw

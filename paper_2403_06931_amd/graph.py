@@ -24,7 +24,7 @@ class ForwardGraph:
         self.cost = torch.empty(b, dtype=torch.float32, device=dev)
         self.end_pos = torch.empty(b, dtype=torch.int64, device=dev)
         self.ws = api.workspace(api.sdtw_forward_workspace_bytes(self.h_lens, reference.numel(),
-                                                                 flags), dev)
+                                                                 flags, variant), dev)
         self.kw = dict(cost=self.cost, end_pos=self.end_pos, flags=flags, variant=variant,
                        workspace_buf=self.ws)
         self.cost_kind = cost_kind

@@ -394,3 +394,25 @@ def test_forward_noalloc_without_a_device(L):
         pytest.skip("a GPU is visible: the placeholder pointers must not reach a kernel")
     rc = _fwd_noalloc(L, [3, 4], ref_len=100)
     assert rc == L.SDTW_ERR_HIP, L.status_string(rc)
+
+
+def test_persistent_grid_flag(L):
+    """The grid-size field of the flags: accepted for 0..8 wavefronts per
+    SIMD, refused above; the persistent workspace holds one row-buffer slot
+    per workgroup of the grid it asks for."""
+    import paper_2403_06931_amd as P
+    small = _variant_of((8, 8, 1, 16, 1))           # 512 rows per pass, one wavefront
+    lens = np.full(10000, 300, np.int32)
+    lens[7] = 3000                                   # one query needs several passes
+    row = -(-1000 // 64) * 64 * 4
+    sizes = {}
+    for wps in (1, 2, 3, 4, 8):
+        f = P.SDTW_F_PERSISTENT | P.SDTW_F_WAVES_PER_SIMD(wps)
+        sizes[wps] = P.sdtw_forward_workspace_bytes(lens, 1000, f, small)
+        assert 256 * 4 * wps * row <= sizes[wps] < 256 * 4 * wps * row + 2 * 10000 * 8 + 4096
+    assert sizes[2] == P.sdtw_forward_workspace_bytes(lens, 1000, P.SDTW_F_PERSISTENT, small)
+    assert P.sdtw_forward_workspace_bytes(
+        lens, 1000, P.SDTW_F_PERSISTENT | P.SDTW_F_WAVES_PER_SIMD(9), small) == 0
+    assert _fwd(L, [3, 4], flags=P.SDTW_F_PERSISTENT | P.SDTW_F_WAVES_PER_SIMD(9)) == \
+        L.SDTW_ERR_INVALID_ARG
+    assert _fwd(L, [3, 4], flags=P.SDTW_F_PERSISTENT | (1 << 12)) == L.SDTW_ERR_INVALID_ARG

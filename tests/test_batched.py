@@ -79,3 +79,25 @@ def test_graph_replays_match_eager():
     torch.cuda.synchronize()
     want_c, want_e = oracle.sdtw_f32(other.queries, other.lens, w.reference, 0)
     assert_bit_exact(c.cpu().numpy(), e.cpu().numpy(), want_c, want_e, "replay after refill")
+
+
+def test_persistent_grid_sizes():
+    """Every persistent grid size (1, 2, 3, 4 and 8 resident wavefronts per
+    SIMD) gives the oracle's results bit for bit, on a ragged batch with
+    multi-pass queries (one row-buffer slot per workgroup) and on more
+    queries than any of the grids has workgroups."""
+    import paper_2403_06931_amd as P
+    lens = [1, 5, 64, 65, 700, 2049, 300, 4000, 3, 1500, 513, 2600, 90, 1, 8, 1024]
+    w = workloads.make_random(len(lens), lens, 3001, seed=613)
+    want_c, want_e = oracle.sdtw_f32(w.queries, w.lens, w.reference, 0)
+    rng = np.random.default_rng(7)
+    many = workloads.make_random(9000, list(rng.integers(1, 120, 9000)), 400, seed=614)
+    many_c, many_e = oracle.sdtw_f32(many.queries, many.lens, many.reference, 0)
+    for v in (6, 1):     # one-wavefront and four-wavefront tiles
+        for wps in (1, 2, 3, 4, 8):
+            flags = P.SDTW_F_PERSISTENT | P.SDTW_F_WAVES_PER_SIMD(wps)
+            print(f"variant {P.sdtw_variant_info(v)} {wps} waves per SIMD", flush=True)
+            c, e = gpu_forward(w, 0, variant=v, flags=flags)
+            assert_bit_exact(c, e, want_c, want_e, f"variant {v}, {wps} per SIMD")
+            c, e = gpu_forward(many, 0, variant=v, flags=flags)
+            assert_bit_exact(c, e, many_c, many_e, f"9000 queries, variant {v}, {wps} per SIMD")
