@@ -170,7 +170,10 @@ def sample_sclk(run, launches, torch):
     vals = sorted(v for v in samples if isinstance(v, (int, float)) and v > 0)
     if not vals:
         return None
-    return {"ghz": vals[len(vals) // 2] / 1000.0, "samples": len(vals),
+    # samples taken while the GPU was busy: a profiler that serialises the
+    # launches leaves the GPU idle (at its idle clock) between them
+    busy = [v for v in vals if v >= 0.5 * vals[-1]]
+    return {"ghz": busy[len(busy) // 2] / 1000.0, "samples": len(vals), "busy_samples": len(busy),
             "min_ghz": vals[0] / 1000.0, "max_ghz": vals[-1] / 1000.0}
 
 

@@ -177,6 +177,7 @@ struct PassGeom {
   int tiles_per_ckpt;
   bool ck_each_step;                         // store checkpoints every step
   bool final_pass;                           // the stored row is row N
+  bool idle;                                 // every row of this wave is past row N
   int64_t qoff;
   float* row;                                // row-buffer slot of the query
   float* s_out;                              // LDS: row N over one interval
@@ -391,13 +392,20 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>&
   for (int it = 0; it < G.nint; ++it) {
     Stager<R, T, W, KS, XL, V> st;
     st.load(p.reference, p.ref_len, prev_row, G.ntiles * T, (it + 2) * KS, tid);
+    // A wave whose rows all lie past row N (the last pass of a query that
+    // does not fill it) computes nothing: nothing flows upward, so its cells
+    // are never read.  It still stages its share of the reference and meets
+    // every barrier; its issue slots go to the other waves on its SIMD.
+    if (!G.idle) {
 #pragma unroll 1
-    for (int s = 0; s < KS; s += 2) {
-      const int g = it * KS + s;
-      step_inputs<R, T, W, KS, XL>(rvB, injB, g + 1, G, s_ref, s_hand, s_slot);
-      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvA, injA, g, s_hand, s_slot);
-      step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
-      fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
+      for (int s = 0; s < KS; s += 2) {
+        const int g = it * KS + s;
+        step_inputs<R, T, W, KS, XL>(rvB, injB, g + 1, G, s_ref, s_hand, s_slot);
+        fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvA, injA, g, s_hand, s_slot);
+        step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
+        fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvB, injB, g + 1, s_hand,
+                                                       s_slot);
+      }
     }
     // The stager's commit waits for its loads with a vmcnt wait, which on
     // gfx950 also covers every store issued before it; the interval's global
@@ -449,6 +457,7 @@ __device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom
   using In = typename Val<V>::In;
   const int tid = threadIdx.x;
   G.row0 = prow0 + pos * RR;                           // first row of this lane
+  G.idle = prow0 + G.wave * kWave * RR >= G.n;         // uniform: wave and lengths
   LaneState<RR, T, V> L;
 #pragma unroll
   for (int k = 0; k < RR; ++k) {
