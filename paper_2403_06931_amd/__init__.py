@@ -8,7 +8,7 @@ include/sdtw.h (libsdtw.so).  This package is the thin Python binding over
 that library.
 """
 from .api import (SDTW_COST_ABSOLUTE, SDTW_COST_SQUARED, SDTW_F_CHECKPOINT,  # noqa: F401
-                  SDTW_F_PERSISTENT, SDTW_F_WAVES_PER_SIMD, SdtwError, sdtw_align, sdtw_align_workspace_bytes,
+                  SDTW_F_PERSISTENT, SDTW_F_WAVES_PER_SIMD, SDTW_ROW_CKPT_EVERY, SdtwError, sdtw_align, sdtw_align_workspace_bytes,
                   sdtw_backward, sdtw_backward_workspace_bytes,
                   sdtw_checkpoint_floats, sdtw_default_variant, sdtw_forward,
                   sdtw_forward_f16, sdtw_forward_f16_workspace_bytes, sdtw_forward_noalloc,

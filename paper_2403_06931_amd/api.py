@@ -23,7 +23,8 @@ import torch
 
 from . import _lib
 from ._lib import (SDTW_COST_ABSOLUTE, SDTW_COST_SQUARED, SDTW_F_CHECKPOINT,  # noqa: F401
-                   SDTW_F_PERSISTENT, SDTW_F_WAVES_PER_SIMD, SdtwError, check)
+                   SDTW_F_PERSISTENT, SDTW_F_WAVES_PER_SIMD, SDTW_ROW_CKPT_EVERY, SdtwError,
+                   check)
 
 _ALIGN = 256
 

@@ -159,6 +159,12 @@ int64_t fwd_slots(const Variant& v, const int32_t* h_lens, int32_t batch, int32_
   return multi;
 }
 
+// Rows of the row-checkpoint region: query b's rows kRowCkpt*k < len_b
+// (k >= 1) sit at region rows offset(b)/kRowCkpt + k - 1, which never
+// overlap the next query's (the floor of a sum bounds the sum of floors).
+static_assert(sdtw::kRowCkpt == SDTW_ROW_CKPT_EVERY, "row-checkpoint spacing");
+int64_t row_ckpt_rows(int64_t total_len) { return total_len / sdtw::kRowCkpt; }
+
 int64_t n_ckpt_of(int64_t ref_len, int32_t every) {
   if (every < 1) return -1;
   return (ref_len + every - 1) / every - 1;
@@ -248,6 +254,12 @@ int pick_variant(const int32_t* h_lens, int32_t batch, int64_t ref_len, int32_t 
 // both are kept under kBwdCodeBudget bytes where the batch allows, with at
 // least one block per round.
 constexpr size_t kBwdCodeBudget = size_t(2) << 30;
+// Round kernels from this one on recompute their blocks as row bands.  The
+// first two recomputes (rounds 0 and 1: every query's first blocks, then
+// those of nearly every query, since round 1's are started before round 0's
+// walk ends) are bound by issue slots, where bands would only add pipeline
+// fill and more wavefronts beside the walkers: whole blocks there.
+constexpr int kFirstBandedKernel = 1;
 
 struct BwdLayout {
   size_t offsets, state, lo, row_lo, row_hi, part, codes, total;
@@ -327,7 +339,8 @@ int launch(const void* fn, dim3 grid, dim3 block, void** args, hipStream_t strea
 sdtw::BwdParams bwd_params(const float* queries, const int32_t* query_lens, int32_t batch,
                            const float* reference, int64_t ref_len, const float* cost,
                            const int64_t* end_pos, const float* ckpt, int32_t ckpt_every,
-                           int64_t nck, int32_t nmax, const BwdLayout& L, void* workspace) {
+                           int64_t nck, int64_t total, int32_t nmax, const BwdLayout& L,
+                           void* workspace) {
   char* ws = static_cast<char*>(workspace);
   int64_t* offs = reinterpret_cast<int64_t*>(ws + L.offsets);
   sdtw::BwdParams p{};
@@ -338,6 +351,7 @@ sdtw::BwdParams bwd_params(const float* queries, const int32_t* query_lens, int3
   p.cost = cost;
   p.end_pos = end_pos;
   p.ckpt = ckpt;
+  p.rowck = nck > 0 ? ckpt + total * nck : nullptr;
   p.ref_part = reinterpret_cast<float*>(ws + L.part);
   p.path_lo = reinterpret_cast<int32_t*>(ws + L.lo);
   p.row_lo = reinterpret_cast<int32_t*>(ws + L.row_lo);
@@ -353,6 +367,7 @@ sdtw::BwdParams bwd_params(const float* queries, const int32_t* query_lens, int3
   p.slots = L.slots;
   p.max_rows = nmax;
   p.round = 0;
+  p.nband = 1;
   p.code_half = L.code_half;
   return p;
 }
@@ -380,22 +395,36 @@ int bwd_walk(sdtw::BwdParams& p, const BwdLayout& L, const int32_t* query_lens, 
                 dim3(sdtw::kInitThreads), args, stream);
     if (rc != SDTW_OK) return rc;
   }
-  const size_t round_lds = sdtw::bwd_round_lds_bytes(nmax);
+  const size_t round_lds = sdtw::bwd_round_lds_bytes(nmax);      // per wavefront
+  const int round_wpg = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / round_lds));
+  // Row bands: later rounds' blocks (few queries still walking, so bound by
+  // one block's latency rather than by issue slots) are recomputed as
+  // bands of kRowCkpt rows from the forward's row checkpoints.
+  const int32_t nband = p.rowck != nullptr ? (nmax + sdtw::kRowCkpt - 1) / sdtw::kRowCkpt : 1;
   {
     const void* dirs = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
                           : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
+    p.nband = 1;
+    // up to four wavefronts per workgroup, each with its own query and left
+    // column in LDS (at most 64 KB per workgroup)
+    const size_t per_wave = sizeof(float) * 2 * (size_t)nmax;
+    const int wpg = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / per_wave));
+    const int64_t items = (int64_t)batch * L.slots;
     void* args[] = {(void*)&p};
-    if (hipLaunchKernel(dirs, dim3(batch, L.slots), dim3(sdtw::kWave), args, round_lds,
-                        stream) != hipSuccess)
+    if (hipLaunchKernel(dirs, dim3((unsigned)((items + wpg - 1) / wpg)), dim3(sdtw::kWave * wpg),
+                        args, per_wave * wpg, stream) != hipSuccess)
       return SDTW_ERR_HIP;
   }
   const void* round_fn = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<0>)
                             : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_round_kernel<1>);
   for (int r = 0; r < L.rounds; ++r) {
     p.round = r;
-    const int64_t grid = (int64_t)batch * (r + 1 < L.rounds ? 1 + L.slots : 1);
+    // (no next round: no recompute wavefronts, padding ones included)
+    p.nband = r + 1 == L.rounds ? 0 : (r >= kFirstBandedKernel ? nband : 1);
+    const int64_t grid = (int64_t)batch * (1 + (int64_t)L.slots * p.nband);
     void* args[] = {(void*)&p};
-    if (hipLaunchKernel(round_fn, dim3((unsigned)grid), dim3(sdtw::kWave), args, round_lds,
+    if (hipLaunchKernel(round_fn, dim3((unsigned)((grid + round_wpg - 1) / round_wpg)),
+                        dim3(sdtw::kWave * round_wpg), args, round_lds * round_wpg,
                         stream) != hipSuccess)
       return SDTW_ERR_HIP;
   }
@@ -469,7 +498,7 @@ size_t sdtw_checkpoint_floats(const int32_t* h_query_lens, int32_t batch, int64_
   if (!lens_ok(h_query_lens, batch, &total, nullptr) || !ref_ok(ref_len) || ckpt_every < 1)
     return 0;
   const int64_t nck = n_ckpt_of(ref_len, ckpt_every);
-  return nck > 0 ? (size_t)(total * nck) : 0;
+  return nck > 0 ? (size_t)(total * nck + row_ckpt_rows(total) * ref_len) : 0;
 }
 
 }  // extern "C"
@@ -531,6 +560,7 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
   p.cost = cost;
   p.end_pos = end_pos;
   p.ckpt = (want_ckpt && nck > 0) ? ckpt : nullptr;
+  p.rowck = p.ckpt != nullptr ? ckpt + total * nck : nullptr;
   p.order = reinterpret_cast<int32_t*>(ws + L.order);
   p.queue = reinterpret_cast<int32_t*>(ws + L.queue);
   p.row_stride = row_stride_floats(ref_len);
@@ -772,7 +802,7 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
 
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   sdtw::BwdParams p = bwd_params(queries, query_lens, batch, reference, ref_len, cost, end_pos,
-                                 ckpt, ckpt_every, nck, nmax, L, workspace);
+                                 ckpt, ckpt_every, nck, total, nmax, L, workspace);
   p.grad_cost = grad_cost;
   p.grad_q = grad_queries;
   const bool sq = cost_kind == SDTW_COST_SQUARED;
@@ -786,7 +816,8 @@ int sdtw_backward(const float* queries, const int32_t* h_query_lens, const int32
            : (qlds ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1, true>)
                    : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_grad_kernel<1, false>));
     void* args[] = {(void*)&p};
-    if (hipLaunchKernel(grad, dim3(batch, 2), dim3(sdtw::kGradThreads), args,
+    const dim3 grid(batch, sdtw::kGradColGroups + sdtw::bwd_grad_row_groups(nmax));
+    if (hipLaunchKernel(grad, grid, dim3(sdtw::kGradThreads), args,
                         sdtw::bwd_grad_lds_bytes(nmax), stream) != hipSuccess)
       return SDTW_ERR_HIP;
   }
@@ -838,7 +869,7 @@ int sdtw_align(const float* queries, const int32_t* h_query_lens, const int32_t*
 
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_ptr);
   sdtw::BwdParams p = bwd_params(queries, query_lens, batch, reference, ref_len, cost, end_pos,
-                                 ckpt, ckpt_every, nck, nmax, L, workspace);
+                                 ckpt, ckpt_every, nck, total, nmax, L, workspace);
   p.ref_part = nullptr;
   p.row_lo = path_lo;                           // the walker writes the bounds in place
   p.row_hi = path_hi;

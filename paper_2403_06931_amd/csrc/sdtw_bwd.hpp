@@ -44,7 +44,7 @@ namespace sdtw {
 constexpr int kDirCols = 16;                    // reference columns per lane
 constexpr int kDirSeg = kWave * kDirCols;       // columns per segment
 constexpr int kDirMaxRows = 8192;               // query + left column held in LDS
-constexpr int kWalkChunk = 64;                  // code rows per walker LDS chunk
+constexpr int kWalkChunk = 32;                  // code rows per walker LDS chunk
 constexpr int kBwdMaxSlots = 8;                 // blocks per round per query
 
 // Direction code of a cell, 2 bits: a = "the diagonal is not a minimum",
@@ -74,6 +74,7 @@ struct BwdParams {
   const float* cost;          // [batch], the forward's
   const int64_t* end_pos;     // [batch]
   const float* ckpt;          // forward checkpoints (nullptr when n_ckpt == 0)
+  const float* rowck;         // the forward's row checkpoints (nullptr when n_ckpt == 0)
   float* grad_q;              // packed like queries
   float* ref_part;            // [batch][part_stride] per-query reference partials
   int32_t* path_lo;           // [batch] first reference column of the path
@@ -90,6 +91,8 @@ struct BwdParams {
   int32_t slots;              // blocks per round (G)
   int32_t max_rows;           // longest query (sizes the LDS of the kernels)
   int32_t round;
+  int32_t nband;              // row bands per recomputed block (1: the whole block;
+                              // 0 in a round kernel with no round after it)
   int64_t code_half;          // words of one code buffer (two alternate by round)
 };
 
@@ -105,12 +108,18 @@ __device__ __forceinline__ int64_t wave_uniform64(int64_t v) {
 // Codes of segment s of round slot t of query b in the code buffer of round
 // r (rounds alternate between two buffers): n + 63 rows of 64 words; word l
 // of row g holds the 16 codes of lane l at step g, i.e. of query row
-// i = g - l + 1 and columns 16l .. 16l+15 of the segment.
+// i = g - l + 1 and columns 16l .. 16l+15 of the segment.  Rows of all the
+// query's segments of a round are interleaved (row g of every segment, then
+// row g+1, ...; code_row_stride words apart), so the wavefronts recomputing
+// one query's blocks side by side write one contiguous stream per step.
+__device__ __forceinline__ int64_t code_row_stride(const BwdParams& p) {
+  return (int64_t)p.slots * p.nseg * kWave;
+}
+
 __device__ __forceinline__ int64_t code_segment(const BwdParams& p, int r, int b, int64_t qoff,
-                                                int n, int t, int s) {
-  const int64_t rows = (int64_t)n + kWave - 1;
-  const int64_t base = (int64_t)p.slots * p.nseg * kWave * (qoff + (int64_t)(kWave - 1) * b);
-  return (r & 1) * p.code_half + base + ((int64_t)t * p.nseg + s) * rows * kWave;
+                                                int t, int s) {
+  const int64_t base = code_row_stride(p) * (qoff + (int64_t)(kWave - 1) * b);
+  return (r & 1) * p.code_half + base + ((int64_t)t * p.nseg + s) * kWave;
 }
 
 // Local-cost derivative with respect to the query value at t = q - r.
@@ -162,7 +171,7 @@ template <int KIND, bool MASKED>
 __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, float il, float iq,
                                           float* ledge, const float (&rv)[kDirCols],
                                           float (&dprev)[kDirCols], float& last, float& shp,
-                                          float& qv, uint32_t* __restrict__ out) {
+                                          float& qv, uint32_t* __restrict__ out, int64_t rs) {
   const float shc = wave_shr1(il, last);          // left neighbour on this row
   qv = wave_shr1(iq, qv);                         // this row's query value
   float cur[kDirCols];
@@ -178,9 +187,13 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, float il, 
     diag = up;
     left = cur[c];
   }
-  out[(int64_t)g * kWave] = word;
   const int i = g - lane + 1;
+  // (a lane outside rows 1..nrows stores nothing: with row bands, those
+  // code words belong to the neighbouring band)
   if (!MASKED || (i >= 1 && i <= nrows)) {
+    // (non-temporal: codes are written once and most are never read, so
+    // they should not displace, or leave dirty, cache lines other kernels use)
+    __builtin_nontemporal_store(word, &out[(int64_t)g * rs]);
 #pragma unroll
     for (int c = 0; c < kDirCols; ++c) dprev[c] = cur[c];
     last = cur[kDirCols - 1];
@@ -194,11 +207,14 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, float il, 
 // Recompute rows 1..i of block slot t of round r of query b (i = the
 // walker's current row as last stored, which only decreases, so any value
 // read is enough; lowered further by the block's right checkpoint column)
-// and store its direction codes.  One wavefront; LDS `dyn`: query
-// values and the left boundary column, 2 * max_rows floats.
+// and store its direction codes.  With p.nband > 1 the block is split into
+// bands of kRowCkpt rows, each recomputed on its own from the forward's row
+// checkpoint above it; this call takes band z.  One wavefront; LDS `dyn`:
+// query values and the left boundary column, 2 * max_rows floats.
 template <int KIND>
-__device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int t, float* dyn) {
-  const int lane = threadIdx.x;
+__device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int t, int z,
+                                           float* dyn) {
+  const int lane = threadIdx.x & (kWave - 1);
   if (wave_uniform(p.state[4 * b + 2]) != 0) return;
   const int K = p.ckpt_every;
   const int64_t e = wave_uniform64(p.end_pos[b]);
@@ -224,15 +240,25 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
     nrows = wave_uniform(last);
     if (nrows == 0) return;                    // the path does not reach this block
   }
+  // band z: rows r0+1 .. r0+brows
+  const int r0 = z * kRowCkpt;
+  if (r0 >= nrows) return;
+  const int brows = p.nband > 1 && r0 + kRowCkpt < nrows ? kRowCkpt : nrows - r0;
   float* lq = dyn;
   float* ledge = dyn + p.max_rows;
-  const float* __restrict__ q = p.queries + qoff;
-  const float* ck = blk > 0 ? p.ckpt + qoff * p.n_ckpt + (int64_t)(blk - 1) * n : nullptr;
-  for (int k = lane; k < nrows; k += kWave) {
+  const float* __restrict__ q = p.queries + qoff + r0;
+  const float* ck = blk > 0 ? p.ckpt + qoff * p.n_ckpt + (int64_t)(blk - 1) * n + r0 : nullptr;
+  for (int k = lane; k < brows; k += kWave) {
     lq[k] = q[k];
     ledge[k] = blk > 0 ? ck[k] : inf_f32();
   }
-  __syncthreads();
+  // (the LDS region is this wavefront's own: a wavefront-level barrier)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // the band's top boundary: row r0 (row 0 = zeros for the first band)
+  const float* top =
+      r0 > 0 ? p.rowck + (qoff / kRowCkpt + z - 1) * (int64_t)p.ref_len : nullptr;
 
   const int bc0 = blk * K;
   const int bend = bc0 + K < p.ref_len ? bc0 + K : p.ref_len;
@@ -246,52 +272,69 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
       const int j = cs + lane * kDirCols + c;
       rv[c] = j < bend ? p.reference[j] : 0.0f;
     }
-    uint32_t* out = p.codes + code_segment(p, r, b, qoff, n, t, s) + lane;
+    // band-local step g stores code row r0 + g
+    const int64_t rs = code_row_stride(p);
+    uint32_t* out = p.codes + code_segment(p, r, b, qoff, t, s) + (int64_t)r0 * rs + lane;
+    // Row r0 of the segment's columns; a lane's `last` is its right-most
+    // value there (lane l+1's diagonal for its first row), and lane 0's
+    // first diagonal is D(r0, cs-1) (+inf left of column 1 below row 0).
     float dprev[kDirCols];
+    float shp = 0.0f;
+    if (top != nullptr) {
 #pragma unroll
-    for (int c = 0; c < kDirCols; ++c) dprev[c] = 0.0f;      // row 0
-    float last = 0.0f, shp = 0.0f, qv = 0.0f;
-    const int g_end = nrows + kWave - 1;
+      for (int c = 0; c < kDirCols; ++c) {
+        const int j = cs + lane * kDirCols + c;
+        dprev[c] = j < p.ref_len ? top[j] : 0.0f;
+      }
+      shp = cs > 0 ? top[cs - 1] : inf_f32();
+    } else {
+#pragma unroll
+      for (int c = 0; c < kDirCols; ++c) dprev[c] = 0.0f;    // row 0
+    }
+    float last = dprev[kDirCols - 1], qv = 0.0f;
+    const int g_end = brows + kWave - 1;
     const int g_head = g_end < kWave - 1 ? g_end : kWave - 1;
     // (lane 63 writes ledge[g-63] at step g, long after it was read)
     float ilA, iqA, ilB, iqB;
-    dirs_inputs(0, nrows, lq, ledge, ilA, iqA);
+    dirs_inputs(0, brows, lq, ledge, ilA, iqA);
     int g = 0;
     for (; g < g_head; ++g) {
-      dirs_inputs(g + 1, nrows, lq, ledge, ilB, iqB);
-      dirs_step<KIND, true>(g, lane, nrows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out);
+      dirs_inputs(g + 1, brows, lq, ledge, ilB, iqB);
+      dirs_step<KIND, true>(g, lane, brows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out, rs);
       ilA = ilB;
       iqA = iqB;
     }
-    for (; g + 1 < nrows; g += 2) {
-      dirs_inputs(g + 1, nrows, lq, ledge, ilB, iqB);
-      dirs_step<KIND, false>(g, lane, nrows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out);
-      dirs_inputs(g + 2, nrows, lq, ledge, ilA, iqA);
-      dirs_step<KIND, false>(g + 1, lane, nrows, ilB, iqB, ledge, rv, dprev, last, shp, qv,
-                             out);
+    for (; g + 1 < brows; g += 2) {
+      dirs_inputs(g + 1, brows, lq, ledge, ilB, iqB);
+      dirs_step<KIND, false>(g, lane, brows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out,
+                             rs);
+      dirs_inputs(g + 2, brows, lq, ledge, ilA, iqA);
+      dirs_step<KIND, false>(g + 1, lane, brows, ilB, iqB, ledge, rv, dprev, last, shp, qv,
+                             out, rs);
     }
     for (; g < g_end; ++g) {
-      dirs_inputs(g + 1, nrows, lq, ledge, ilB, iqB);
-      dirs_step<KIND, true>(g, lane, nrows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out);
+      dirs_inputs(g + 1, brows, lq, ledge, ilB, iqB);
+      dirs_step<KIND, true>(g, lane, brows, ilA, iqA, ledge, rv, dprev, last, shp, qv, out, rs);
       ilA = ilB;
       iqA = iqB;
     }
   }
 }
 
-// Code rows [64k, 64k + 64) of a segment are 4096 consecutive words; each
-// lane holds 16 uint4 of them.  Rows past the segment's end read as zero
-// (they are never addressed).
+// Code rows [64k, 64k + 64) of a segment (rs words apart) staged as 4096
+// consecutive words; each lane holds 16 uint4 of them.  Rows past the
+// segment's end read as zero (they are never addressed).
 struct CodeChunk {
   uint4 v[kWalkChunk * kWave / (4 * kWave)];
 
-  __device__ __forceinline__ void fetch(const uint32_t* seg, int k, int code_rows, int lane) {
+  __device__ __forceinline__ void fetch(const uint32_t* seg, int64_t rs, int k, int code_rows,
+                                        int lane) {
 #pragma unroll
     for (int u = 0; u < kWalkChunk / 4; ++u) {
       const int e = 4 * (lane + kWave * u);             // word within the chunk
       const int row = k * kWalkChunk + e / kWave;
       v[u] = row < code_rows
-                 ? *reinterpret_cast<const uint4*>(seg + (int64_t)k * kWalkChunk * kWave + e)
+                 ? *reinterpret_cast<const uint4*>(seg + (int64_t)row * rs + (e & (kWave - 1)))
                  : make_uint4(0u, 0u, 0u, 0u);
     }
   }
@@ -309,7 +352,7 @@ struct CodeChunk {
 // walk, and falls by at most 2 per move, so the chunk below the current one
 // is always the next one needed and is fetched ahead.
 __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uint32_t* chunk) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
   if (wave_uniform(p.state[4 * b + 2]) != 0) return;
   int i = wave_uniform(p.state[4 * b + 0]);
   int j = wave_uniform(p.state[4 * b + 1]);
@@ -320,6 +363,7 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
   int32_t* rlo = p.row_lo + qoff - 1;           // indexed by 1-based row
   int32_t* rhi = p.row_hi + qoff - 1;
   const int code_rows = n + kWave - 1;
+  const int64_t rs = code_row_stride(p);
   int done = 0;
 
   for (int t = 0; t < p.slots && !done; ++t) {
@@ -328,7 +372,7 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
     const int bc0 = blk * K;
     for (int s = (j - bc0) / kDirSeg; s >= 0 && !done; --s) {
       const int cs = bc0 + s * kDirSeg;
-      const uint32_t* seg = p.codes + code_segment(p, r, b, qoff, n, t, s);
+      const uint32_t* seg = p.codes + code_segment(p, r, b, qoff, t, s);
       CodeChunk pre;                            // the chunk fetched ahead
       int kc = -1, kp = -1;                     // chunk in LDS, chunk in `pre`
       while (j >= cs) {
@@ -337,13 +381,13 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
         const int g = i - 1 + L;
         const int k = g / kWalkChunk;
         if (k != kc) {
-          if (kp != k) pre.fetch(seg, k, code_rows, lane);
+          if (kp != k) pre.fetch(seg, rs, k, code_rows, lane);
           __builtin_amdgcn_wave_barrier();
           pre.commit(chunk, lane);
           __builtin_amdgcn_wave_barrier();
           kc = k;
           kp = k - 1;
-          if (k > 0) pre.fetch(seg, k - 1, code_rows, lane);
+          if (k > 0) pre.fetch(seg, rs, k - 1, code_rows, lane);
         }
         const uint32_t w =
             (uint32_t)wave_uniform((int)chunk[(g - k * kWalkChunk) * kWave + L]);
@@ -382,60 +426,122 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
   }
 }
 
-// Kernel LDS: the larger of the walker's code chunk and the dirs block's
-// query + left column.
+// LDS of one round-kernel wavefront: the larger of the walker's code chunk
+// and the dirs block's query + left column.
 __host__ __device__ constexpr size_t bwd_round_lds_bytes(int max_rows) {
   return sizeof(float) * 2 * (size_t)max_rows > sizeof(uint32_t) * kWalkChunk * kWave
              ? sizeof(float) * 2 * (size_t)max_rows
              : sizeof(uint32_t) * kWalkChunk * kWave;
 }
 
-// Round 0's blocks.  Grid: (batch, slots); one wavefront per workgroup.
+// Round 0's blocks, one wavefront each, blockDim.x / 64 wavefronts per
+// workgroup (each with its own 2 * max_rows floats of LDS): block item
+// e = blockIdx.x * (blockDim.x / 64) + wave is query e % batch, slot
+// e / batch.  (Several wavefronts per workgroup keep the placement even: a
+// grid of as many one-wavefront workgroups as two per SIMD was placed
+// unevenly depending on the kernel before it, up to 1.4 times slower.)
 template <int KIND>
-__global__ __launch_bounds__(kWave) void sdtw_bwd_dirs_kernel(const BwdParams p) {
+__global__ __launch_bounds__(4 * kWave) void sdtw_bwd_dirs_kernel(const BwdParams p) {
   extern __shared__ __attribute__((aligned(16))) float dyn[];
-  dirs_block<KIND>(p, 0, blockIdx.x, blockIdx.y, dyn);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int e = (int)blockIdx.x * (int)(blockDim.x / kWave) + w;
+  if (e >= p.batch * p.slots) return;
+  dirs_block<KIND>(p, 0, e % p.batch, e / p.batch, 0, dyn + (size_t)w * 2 * p.max_rows);
 }
 
-// Round r = p.round: workgroups [0, batch) walk round r; when another round
-// follows, workgroups [batch, batch + batch * slots) recompute round r+1's
-// blocks into the other code buffer meanwhile.  One wavefront per workgroup.
+// Round r = p.round: wavefronts [0, batch) walk round r; when another round
+// follows, wavefronts [batch, batch + batch * slots * nband) recompute round
+// r+1's blocks (row bands) into the other code buffer meanwhile.  Wavefront
+// e = blockIdx.x * (blockDim.x / 64) + wave, each with its own
+// bwd_round_lds_bytes(max_rows) of LDS (several wavefronts per workgroup
+// keep the placement on the SIMDs even).
 template <int KIND>
-__global__ __launch_bounds__(kWave) void sdtw_bwd_round_kernel(const BwdParams p) {
+__global__ __launch_bounds__(4 * kWave) void sdtw_bwd_round_kernel(const BwdParams p) {
   extern __shared__ __attribute__((aligned(16))) float dyn[];
-  const int x = blockIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+  const int x = (int)blockIdx.x * (int)(blockDim.x / kWave) + w;
+  float* mine = dyn + (size_t)w * (bwd_round_lds_bytes(p.max_rows) / sizeof(float));
   if (x < p.batch) {
-    walk_query(p, p.round, x, reinterpret_cast<uint32_t*>(dyn));
+    walk_query(p, p.round, x, reinterpret_cast<uint32_t*>(mine));
   } else {
     const int k = x - p.batch;
-    dirs_block<KIND>(p, p.round + 1, k % p.batch, k / p.batch, dyn);
+    const int tz = k / p.batch;
+    if (tz < p.slots * p.nband)
+      dirs_block<KIND>(p, p.round + 1, k % p.batch, tz / p.nband, tz % p.nband, mine);
   }
 }
 
-// Gradients from the recorded path rows.  Grid: (batch, 2): blockIdx.y = 0
-// takes the query sums, 1 the reference partials (independent, so they run
-// side by side); kGradThreads threads;
-// dynamic LDS: the row bounds (2 * max_rows ints) and, with QLDS, the query
-// values (max_rows floats).  Row i's path columns are [row_lo[i], row_hi[i]];
+// Gradients from the recorded path rows.  Grid: (batch, RG + kGradColGroups),
+// RG = ceil(max_rows / kGradThreads), kGradThreads threads.  blockIdx.y = y
+// < RG takes the query sums of rows y*kGradThreads + 1 .., one thread per row
+// (dispatched first: their longest runs are the kernel's longest chains);
+// blockIdx.y = RG + g takes the reference partials of share g of
+// kGradColGroups equal shares of the query's column span, with the row
+// bounds (2 * max_rows ints) and, with QLDS, the query values (max_rows
+// floats) in dynamic LDS.  Row i's path
+// columns are [row_lo[i], row_hi[i]];
 // both bounds are nondecreasing in i, so the rows of column j are the run
 // from its top row (the first row with row_hi >= j) down to its bottom row
 // (the last row with row_lo <= j).
-//   grad_q[i]      = sum over row i's columns j (descending) of g*dc/dq,
-//                    one thread per row;
+//   grad_q[i]      = sum over row i's columns j (descending) of g*dc/dq;
 //   ref_part[b][j] = sum over column j's rows i (descending) of -g*dc/dq,
 //                    for j in [path_lo, end_pos], each thread a contiguous
 //                    range of columns, following the top row along it.
-// Reference values are loaded in batches ahead of the sequential sums.
+// Reference values are loaded in batches, the next batch while the current
+// one is summed.
 constexpr int kGradThreads = 256;
+constexpr int kGradColGroups = 8;               // workgroups per query for column sums
 constexpr int kGradBatch = 8;                   // column sums
-constexpr int kGradRowBatch = 32;               // row sums (runs can be long)
+constexpr int kGradRowBatch = 16;               // row sums from global memory
+constexpr int kGradRowBatchLds = 16;            // row sums from LDS
+
+constexpr int kGradRowLds = 8192;               // reference values a row group stages
 
 __host__ __device__ constexpr bool bwd_grad_q_in_lds(int max_rows) {
   return sizeof(int32_t) * 3 * (size_t)max_rows <= 65536;
 }
 
 __host__ __device__ constexpr size_t bwd_grad_lds_bytes(int max_rows) {
-  return sizeof(int32_t) * (bwd_grad_q_in_lds(max_rows) ? 3 : 2) * (size_t)max_rows;
+  return sizeof(int32_t) * (bwd_grad_q_in_lds(max_rows) ? 3 : 2) * (size_t)max_rows >
+                 sizeof(float) * (size_t)kGradRowLds
+             ? sizeof(int32_t) * (bwd_grad_q_in_lds(max_rows) ? 3 : 2) * (size_t)max_rows
+             : sizeof(float) * (size_t)kGradRowLds;
+}
+
+// grad_q[i] of one row: the run of columns hi, hi-1, .., lo (src[j - off]
+// is the reference value of column j), in batches of B loaded one batch
+// ahead.
+template <int KIND, int B>
+__device__ __forceinline__ float row_sum(const float* __restrict__ src, int off, float qi,
+                                         float gcost, int lo, int jj) {
+  float acc = 0.0f;
+  float rv[B], nx[B];
+#pragma unroll
+  for (int u = 0; u < B; ++u) nx[u] = src[(jj - u >= lo ? jj - u : lo) - off];
+  while (jj - (B - 1) >= lo) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) rv[u] = nx[u];
+    const int jn = jj - B;
+#pragma unroll
+    for (int u = 0; u < B; ++u) nx[u] = src[(jn - u >= lo ? jn - u : lo) - off];
+#pragma unroll
+    for (int u = 0; u < B; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
+    jj = jn;
+  }
+  // the last, partial batch: columns jj .. lo (fewer than B)
+  const int rem = jj - lo;
+#pragma unroll
+  for (int u = 0; u < B - 1; ++u)
+    if (u <= rem) acc = acc + gcost * dcost_dq<KIND>(qi, nx[u]);
+  return acc;
+}
+
+__host__ __device__ constexpr int bwd_grad_row_groups(int max_rows) {
+  return (max_rows + kGradThreads - 1) / kGradThreads;
+}
+
+__device__ __forceinline__ int clamp_col(int v, int lo, int hi) {
+  return v > lo ? (v < hi ? v : hi) : lo;
 }
 
 template <int KIND, bool QLDS>
@@ -447,58 +553,52 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
   const int64_t qoff = p.offsets[b];
   const float* __restrict__ r = p.reference;
   const float gcost = p.grad_cost[b];
-  float* __restrict__ gq = p.grad_q + qoff;
-  float* __restrict__ part = p.ref_part + (int64_t)b * p.part_stride;
   // (the clamps only keep every access in bounds; a finished walk records
   // every row, with columns in [path_lo, end_pos])
   const int jhi = (int)p.end_pos[b];
   const int jlo = p.path_lo[b] > 0 ? (p.path_lo[b] < jhi ? p.path_lo[b] : jhi) : 0;
+
+  const int row_groups = bwd_grad_row_groups(p.max_rows);
+  if ((int)blockIdx.y < row_groups) {
+    // rows i0 .. i0+255: row bounds never decrease with the row, so their
+    // columns are the one span [lo(i0), hi(last row)], staged in LDS when it
+    // fits (values left of a row's lo are loaded but never added)
+    const int i0 = blockIdx.y * kGradThreads + 1;
+    if (i0 > n) return;
+    const int ilast = i0 + kGradThreads - 1 < n ? i0 + kGradThreads - 1 : n;
+    const int slo = clamp_col(p.row_lo[qoff + i0 - 1], jlo, jhi);
+    const int shi = clamp_col(p.row_hi[qoff + ilast - 1], jlo, jhi);
+    const bool staged = shi - slo < kGradRowLds;
+    float* lr = reinterpret_cast<float*>(dyn_rows);
+    if (staged) {
+      for (int e = tid; e <= shi - slo; e += kGradThreads) lr[e] = r[slo + e];
+      __syncthreads();
+    }
+    const int i = i0 + tid;
+    if (i > n) return;
+    const float qi = p.queries[qoff + i - 1];
+    const int lo = clamp_col(p.row_lo[qoff + i - 1], jlo, jhi);
+    const int hi = clamp_col(p.row_hi[qoff + i - 1], jlo, jhi);
+    p.grad_q[qoff + i - 1] = staged ? row_sum<KIND, kGradRowBatchLds>(lr, slo, qi, gcost, lo, hi)
+                                    : row_sum<KIND, kGradRowBatch>(r, 0, qi, gcost, lo, hi);
+    return;
+  }
+
+  float* __restrict__ part = p.ref_part + (int64_t)b * p.part_stride;
   int32_t* rlo = dyn_rows - 1;                  // indexed by 1-based row
   int32_t* rhi = dyn_rows + p.max_rows - 1;
   float* lq = reinterpret_cast<float*>(dyn_rows + 2 * p.max_rows);
   for (int i = 1 + tid; i <= n; i += kGradThreads) {
-    const int lo = p.row_lo[qoff + i - 1];
-    const int hi = p.row_hi[qoff + i - 1];
-    rlo[i] = lo > jlo ? (lo < jhi ? lo : jhi) : jlo;
-    rhi[i] = hi > jlo ? (hi < jhi ? hi : jhi) : jlo;
+    rlo[i] = clamp_col(p.row_lo[qoff + i - 1], jlo, jhi);
+    rhi[i] = clamp_col(p.row_hi[qoff + i - 1], jlo, jhi);
     if constexpr (QLDS) lq[i - 1] = p.queries[qoff + i - 1];
   }
   __syncthreads();
   const float* __restrict__ q = QLDS ? lq : p.queries + qoff;
 
-  if (blockIdx.y == 0) {
-    for (int i = 1 + tid; i <= n; i += kGradThreads) {
-      const float qi = q[i - 1];
-      const int lo = rlo[i];
-      float acc = 0.0f;
-      int jj = rhi[i];
-      // batches of reference values, the next one loaded while this one is
-      // summed (a row's run can be thousands of columns long)
-      float rv[kGradRowBatch], nx[kGradRowBatch];
-      if (jj - (kGradRowBatch - 1) >= lo) {
-#pragma unroll
-        for (int u = 0; u < kGradRowBatch; ++u) nx[u] = r[jj - u];
-      }
-      for (; jj - (kGradRowBatch - 1) >= lo; jj -= kGradRowBatch) {
-#pragma unroll
-        for (int u = 0; u < kGradRowBatch; ++u) rv[u] = nx[u];
-        const int jn = jj - kGradRowBatch;
-        if (jn - (kGradRowBatch - 1) >= lo) {
-#pragma unroll
-          for (int u = 0; u < kGradRowBatch; ++u) nx[u] = r[jn - u];
-        }
-#pragma unroll
-        for (int u = 0; u < kGradRowBatch; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
-      }
-      for (; jj >= lo; --jj) acc = acc + gcost * dcost_dq<KIND>(qi, r[jj]);
-      gq[i - 1] = acc;
-    }
-    return;
-  }
-
   const int span = jhi - jlo + 1;
-  const int per = (span + kGradThreads - 1) / kGradThreads;
-  const int j0 = jlo + tid * per;
+  const int per = (span + kGradColGroups * kGradThreads - 1) / (kGradColGroups * kGradThreads);
+  const int j0 = jlo + ((blockIdx.y - row_groups) * kGradThreads + tid) * per;
   const int j1 = j0 + per < jhi + 1 ? j0 + per : jhi + 1;
   if (j0 < j1) {
     int a = 1, z = n;                           // top row of column j0
@@ -517,11 +617,29 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
         const int jj = jb + u;
         if (jj < j1) {
           while (top < n && rhi[top] < jj) qtop = q[(++top) - 1];
+          // bottom row of column jj: the last row whose first column is <= jj
+          // (first columns never decrease with the row; a binary search for
+          // the rare vertical runs)
           int bottom = top;
-          while (bottom < n && rlo[bottom + 1] <= jj) ++bottom;
+          if (bottom < n && rlo[bottom + 1] <= jj) {
+            int a = bottom + 1, z = n;
+            while (a < z) {
+              const int mid = (a + z + 1) >> 1;
+              if (rlo[mid] <= jj) a = mid; else z = mid - 1;
+            }
+            bottom = a;
+          }
+          // rows bottom, bottom-1, .., top, query values read 8 at a time
           float acc = 0.0f;
-          for (int ii = bottom; ii > top; --ii)
-            acc = acc + (-(gcost * dcost_dq<KIND>(q[ii - 1], rv[u])));
+          int ii = bottom;
+          for (; ii - 7 > top; ii -= 8) {
+            float qv[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) qv[v] = q[ii - v - 1];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) acc = acc + (-(gcost * dcost_dq<KIND>(qv[v], rv[u])));
+          }
+          for (; ii > top; --ii) acc = acc + (-(gcost * dcost_dq<KIND>(q[ii - 1], rv[u])));
           part[jj] = acc + (-(gcost * dcost_dq<KIND>(qtop, rv[u])));
         }
       }
@@ -530,13 +648,22 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
 }
 
 // grad_reference[j] = sum over queries b (increasing) whose path covers
-// column j of ref_part[b][j]; +0 where no path passes.  The partials of
-// kRefReduceBatch queries are loaded at once (entries outside a query's
-// span were never written and are replaced by +0 before the add; the
-// running sum starts at +0 and is never -0, so adding +0 leaves it
-// unchanged and the result equals the sum over covering queries only).
+// column j of ref_part[b][j]; +0 where no path passes.  Only entries inside
+// a query's span [path_lo, end_pos] are loaded (the others were never
+// written) and the rest read as +0; the running sum starts at +0 and is
+// never -0, so adding +0 leaves it unchanged and the result equals the sum
+// over covering queries only.  The next kRefReduceBatch queries' entries
+// are loaded while the current ones are added.
 constexpr int kRefReduceThreads = 256;
-constexpr int kRefReduceBatch = 8;
+constexpr int kRefReduceBatch = 64;
+
+__device__ __forceinline__ float ref_part_at(const float* __restrict__ ref_part,
+                                             int64_t part_stride, const int32_t* __restrict__ lo,
+                                             const int64_t* __restrict__ hi, int32_t batch, int b,
+                                             int j) {
+  return b < batch && j >= lo[b] && j <= (int)hi[b] ? ref_part[(int64_t)b * part_stride + j]
+                                                    : 0.0f;
+}
 
 __global__ __launch_bounds__(kRefReduceThreads) void sdtw_ref_reduce_kernel(
     const float* __restrict__ ref_part, int64_t part_stride, const int32_t* __restrict__ lo,
@@ -544,18 +671,20 @@ __global__ __launch_bounds__(kRefReduceThreads) void sdtw_ref_reduce_kernel(
   const int j = blockIdx.x * kRefReduceThreads + threadIdx.x;
   if (j >= ref_len) return;
   float acc = 0.0f;
-  int b = 0;
-  for (; b + kRefReduceBatch <= batch; b += kRefReduceBatch) {
-    float v[kRefReduceBatch];
+  float v[kRefReduceBatch], nv[kRefReduceBatch];
 #pragma unroll
-    for (int u = 0; u < kRefReduceBatch; ++u)
-      v[u] = ref_part[(int64_t)(b + u) * part_stride + j];
+  for (int u = 0; u < kRefReduceBatch; ++u)
+    nv[u] = ref_part_at(ref_part, part_stride, lo, hi, batch, u, j);
+  for (int b = 0; b < batch; b += kRefReduceBatch) {
 #pragma unroll
-    for (int u = 0; u < kRefReduceBatch; ++u)
-      acc = acc + ((j >= lo[b + u] && j <= (int)hi[b + u]) ? v[u] : 0.0f);
-  }
-  for (; b < batch; ++b) {
-    if (j >= lo[b] && j <= (int)hi[b]) acc = acc + ref_part[(int64_t)b * part_stride + j];
+    for (int u = 0; u < kRefReduceBatch; ++u) v[u] = nv[u];
+    if (b + kRefReduceBatch < batch) {
+#pragma unroll
+      for (int u = 0; u < kRefReduceBatch; ++u)
+        nv[u] = ref_part_at(ref_part, part_stride, lo, hi, batch, b + kRefReduceBatch + u, j);
+    }
+#pragma unroll
+    for (int u = 0; u < kRefReduceBatch; ++u) acc = acc + v[u];
   }
   grad_ref[j] = acc;
 }

@@ -61,6 +61,7 @@ struct FwdParams {
   float* cost;              // [batch]   (written by the argmin kernel)
   int64_t* end_pos;         // [batch]
   float* ckpt;              // checkpoint columns, or nullptr
+  float* rowck;             // row checkpoints (with ckpt), or nullptr
   const int32_t* order;     // persistent form: queries in processing order
   int32_t* queue;           // persistent form: work counter, else nullptr
   int64_t row_stride;       // floats per row-buffer slot (>= ceil(M/T)*T)
@@ -178,6 +179,7 @@ struct PassGeom {
   bool ck_each_step;                         // store checkpoints every step
   bool final_pass;                           // the stored row is row N
   bool idle;                                 // every row of this wave is past row N
+  float* rowck;                              // row checkpoint this wave copies, or nullptr
   int64_t qoff;
   float* row;                                // row-buffer slot of the query
   float* s_out;                              // LDS: row N over one interval
@@ -192,7 +194,7 @@ __device__ __forceinline__ void ckpt_store(const FwdParams& p, LaneState<R, T>& 
     float* dst = p.ckpt + G.qoff * p.n_ckpt + (int64_t)L.ck_k * G.n + G.row0;
 #pragma unroll
     for (int k = 0; k < R; ++k)
-      if (G.row0 + k < G.n) dst[k] = v[k];
+      if (G.row0 + k < G.n) __builtin_nontemporal_store(v[k], &dst[k]);
   }
   L.ck_h += G.tiles_per_ckpt;
   ++L.ck_k;
@@ -205,6 +207,35 @@ template <int R, int T, int KS>
 __device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& L,
                                            const PassGeom& G, int it) {
   if (L.ck_h < (it + 1) * KS) ckpt_store(p, L, G, L.ckv);
+}
+
+// Row checkpoints D(kRowCkpt*k, 1..M) for every multiple of kRowCkpt below
+// N.  Such a row is always a bottom row handed over through a handoff ring:
+// kRowCkpt is a multiple of 64*R for every R (and R/2, R/4), so within a
+// pass it is the bottom row of a wavefront, or else the last row of a pass,
+// which the next pass stages into wavefront 0's ring.  The wavefront whose
+// ring carries it copies the tiles it read in barrier interval `it` to
+// global memory at the interval's end (a tile stays in the ring for two
+// more intervals after its read).  Checkpoint stores are non-temporal: the
+// backward reads a fraction of them, later, and they should not leave the
+// caches full of dirty lines.
+template <int T, int KS, int SH>
+__device__ __forceinline__ void rowck_copy(const FwdParams& p, const PassGeom& G,
+                                           const float* s_hand, int it) {
+  const float* ring = s_hand + G.wave * SH * T;
+  const int tau0 = it * KS - G.lane0_delay;
+#pragma unroll
+  for (int e0 = 0; e0 < KS * T; e0 += kWave) {
+    const int e = e0 + G.lane;
+    if (e < KS * T) {
+      const int tau = tau0 + e / T;
+      const int col = tau * T + (e & (T - 1));
+      if (tau >= 0 && col < p.ref_len) {
+        const float v = ring[(tau & (SH - 1)) * T + (e & (T - 1))];
+        __builtin_nontemporal_store(v, &G.rowck[col]);
+      }
+    }
+  }
 }
 
 // One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
@@ -373,9 +404,13 @@ __device__ __forceinline__ void out_fold(ValIdx (&am)[Val<V>::N], const PassGeom
 // (a pass's last row, read by the next pass).
 template <int T, int KS>
 __device__ __forceinline__ void out_copy(const PassGeom& G, int it) {
+  // (non-temporal: the next pass reads these values a whole pass later,
+  // long after they would have left the caches; cached, they would only
+  // displace the reference tiles every workgroup re-reads)
   for (int e = G.lane; e < KS * T; e += kWave) {
     const int tau = it * KS + e / T - G.out_delay;
-    if (tau >= 0 && tau < G.ntiles) G.row[tau * T + e % T] = G.s_out[e];
+    if (tau >= 0 && tau < G.ntiles)
+      __builtin_nontemporal_store(G.s_out[e], &G.row[tau * T + e % T]);
   }
 }
 
@@ -414,6 +449,9 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>&
     st.commit(s_ref, s_hand, (it + 2) * KS, tid);
     if constexpr (CKPT) {
       if (!G.ck_each_step) ckpt_flush<R, T, KS>(p, L, G, it);
+      if (G.rowck != nullptr)
+        rowck_copy<T, KS, FwdShape<R, T, W, KS, XL>::SH>(p, G, reinterpret_cast<float*>(s_hand),
+                                                          it);
     }
     if constexpr (OUTK >= 0) {
       if (G.final_pass) {
@@ -458,6 +496,11 @@ __device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom
   const int tid = threadIdx.x;
   G.row0 = prow0 + pos * RR;                           // first row of this lane
   G.idle = prow0 + G.wave * kWave * RR >= G.n;         // uniform: wave and lengths
+  // the row above this wave's first row, if it is a row checkpoint
+  const int bnd = prow0 + G.wave * kWave * RR;
+  G.rowck = CKPT && p.rowck != nullptr && bnd > 0 && bnd % kRowCkpt == 0 && bnd < G.n
+                ? p.rowck + (G.qoff / kRowCkpt + bnd / kRowCkpt - 1) * (int64_t)p.ref_len
+                : nullptr;
   LaneState<RR, T, V> L;
 #pragma unroll
   for (int k = 0; k < RR; ++k) {

@@ -2,7 +2,9 @@
 (every K reference columns) equal the oracle's DP columns bit for bit, for
 every compiled variant, several K (both ways the kernel finds the checkpoint
 column, and stores per step or per barrier interval) and queries that need
-several row passes."""
+several row passes; so do the row checkpoints (every 512 rows), which reach
+the store through wavefront handoffs or, between row passes, through the row
+buffer."""
 import numpy as np
 import pytest
 import torch
@@ -38,13 +40,62 @@ def test_checkpoint_columns_all_variants(kind):
     q, l, r = to_dev(w)
     for K in (16, 64, 256, 1024):
         want, nck = _expected(rows, K)
-        assert P.sdtw_checkpoint_floats(w.lens, REF_LEN, K) == want.size
+        size = P.sdtw_checkpoint_floats(w.lens, REF_LEN, K)
+        assert size == want.size + (sum(LENS) // 512) * REF_LEN
         for v in range(P.sdtw_variant_count()):
             print(f"kind {kind} K {K} variant {v} {P.sdtw_variant_info(v)}", flush=True)
-            ckpt = torch.full((want.size,), float("nan"), dtype=torch.float32, device=q.device)
+            ckpt = torch.full((size,), float("nan"), dtype=torch.float32, device=q.device)
             P.sdtw_forward(q, w.lens, l, r, kind, ckpt=ckpt, ckpt_every=K, variant=v,
                            flags=P.SDTW_F_CHECKPOINT)
-            got = ckpt.cpu().numpy()
+            got = ckpt.cpu().numpy()[:want.size]
             bad = np.nonzero(got.view(np.uint32) != want.view(np.uint32))[0]
             assert bad.size == 0, (f"K {K} variant {v}: {bad.size} checkpoint values differ, "
                                    f"first at {bad[:4]}: {got[bad[:4]]} vs {want[bad[:4]]}")
+
+
+ROW_LENS = [1100, 300, 2050, 513, 512, 1536, 1537]
+ROW_REF = 3000
+
+
+def _row_expected(w, kind):
+    """{region row: D(512k, 1..M)} for every row checkpoint of the batch."""
+    step = 512
+    off, rows = 0, {}
+    for b in range(w.batch):
+        n = w.lens[b]
+        for k in range(1, (n - 1) // step + 1):
+            rows[off // step + k - 1] = oracle.last_row_f32(w.query(b)[:k * step], w.reference,
+                                                            kind)
+        off += n
+    return rows
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_row_checkpoints_all_variants(kind):
+    import paper_2403_06931_amd as P
+    assert P.SDTW_ROW_CKPT_EVERY == 512
+    w = workloads.make_random(len(ROW_LENS), ROW_LENS, ROW_REF, seed=91 + kind)
+    rows = _row_expected(w, kind)
+    total = sum(ROW_LENS)
+    q, l, r = to_dev(w)
+    for K in (64, 1024):
+        nck = (ROW_REF + K - 1) // K - 1
+        size = P.sdtw_checkpoint_floats(w.lens, ROW_REF, K)
+        assert size == total * nck + (total // 512) * ROW_REF
+        base = total * nck
+        cases = [(v, P.SDTW_F_CHECKPOINT) for v in range(P.sdtw_variant_count())]
+        cases += [(v, P.SDTW_F_CHECKPOINT | P.SDTW_F_PERSISTENT) for v in (0, 6, 12)]
+        for v, flags in cases:
+            print(f"kind {kind} K {K} variant {v} {P.sdtw_variant_info(v)} flags {flags}",
+                  flush=True)
+            ckpt = torch.full((size,), float("nan"), dtype=torch.float32, device=q.device)
+            P.sdtw_forward(q, w.lens, l, r, kind, ckpt=ckpt, ckpt_every=K, variant=v,
+                           flags=flags)
+            got = ckpt.cpu().numpy()[base:].reshape(-1, ROW_REF)
+            for k in range(got.shape[0]):
+                if k in rows:
+                    bad = np.nonzero(got[k].view(np.uint32) != rows[k].view(np.uint32))[0]
+                    assert bad.size == 0, (f"K {K} variant {v} flags {flags}: region row {k}: "
+                                           f"{bad.size} values differ, first at {bad[:4]}")
+                else:
+                    assert np.isnan(got[k]).all(), f"region row {k} is owned by no query"

@@ -39,9 +39,19 @@ def _run_pair(P, w, kind, flags=0, variant=-1, ckpt_every=0):
     assert np.array_equal(ca.cpu().numpy().view(np.uint32), cb.cpu().numpy().view(np.uint32))
     assert np.array_equal(ea.cpu().numpy(), eb.cpu().numpy())
     if ck_a is not None:
-        need = P.sdtw_checkpoint_floats(w.lens, w.ref_len, ckpt_every)
-        assert np.array_equal(ck_a[:need].cpu().numpy().view(np.uint32),
-                              ck_b[:need].cpu().numpy().view(np.uint32))
+        # every checkpoint column, then the row checkpoints of each query
+        # (rows of the row region that no query owns are never written)
+        a = ck_a.cpu().numpy().view(np.uint32)
+        b = ck_b.cpu().numpy().view(np.uint32)
+        total = int(w.lens.sum())
+        cols = total * ((w.ref_len + ckpt_every - 1) // ckpt_every - 1)
+        assert np.array_equal(a[:cols], b[:cols])
+        step, off = P.SDTW_ROW_CKPT_EVERY, 0
+        for n in w.lens:
+            for k in range(1, (int(n) - 1) // step + 1):
+                at = cols + (off // step + k - 1) * w.ref_len
+                assert np.array_equal(a[at:at + w.ref_len], b[at:at + w.ref_len])
+            off += int(n)
 
 
 def _variant_of(P, shape):
