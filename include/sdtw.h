@@ -73,18 +73,19 @@ enum {
 enum {
     /* Store DP column checkpoints for sdtw_backward (ckpt must be non-NULL). */
     SDTW_F_CHECKPOINT = 1,
-    /* Persistent launch: a fixed grid of workgroups pops queries from a
-     * device work queue, longest first.  Meant for batches of uneven lengths;
-     * the launch sequence is safe to capture in a HIP graph. */
+    /* Persistent launch: a fixed grid of teams (W wavefronts each) pops
+     * queries from a device work queue, longest first.  Meant for batches of
+     * uneven lengths; the launch sequence is safe to capture in a HIP graph. */
     SDTW_F_PERSISTENT = 2
 };
 
 /* Size of the persistent grid, in flags bits 8..11: SDTW_F_WAVES_PER_SIMD(n)
- * asks for n resident wavefronts per SIMD (n = 1..8; 0 or absent: 2), i.e. a
- * grid of min(batch, CUs * 4 * n / W) workgroups of W wavefronts.  Ignored
- * without SDTW_F_PERSISTENT.  The grid size changes the workspace (one
- * row-buffer slot per workgroup when a query needs several passes), never
- * the results. */
+ * asks for n resident wavefronts per SIMD (n = 1..8; 0 or absent: 2), i.e.
+ * min(batch, CUs * 4 * n / W) teams of W wavefronts, four teams to a
+ * workgroup when W = 1 (one otherwise).  Ignored without SDTW_F_PERSISTENT.
+ * The grid size changes the workspace (one row-buffer slot per team of the
+ * grid, rounded up to whole workgroups, when a query needs several passes),
+ * never the results. */
 #define SDTW_F_WAVES_SHIFT 8
 #define SDTW_F_WAVES_MASK (0xf << SDTW_F_WAVES_SHIFT)
 #define SDTW_F_WAVES_PER_SIMD(n) ((int32_t)(n) << SDTW_F_WAVES_SHIFT)
@@ -104,7 +105,7 @@ enum {
  * row pass to the next pass.  A pass covers 64 * R * W query rows (R rows per
  * lane, W wavefronts per query: sdtw_variant_info); the plain launch gives a
  * slot to each query longer than one pass, the persistent launch one to each
- * of its workgroups when some query is.  A batch whose queries all fit in
+ * of its teams when some query is.  A batch whose queries all fit in
  * one pass needs no row buffer.  cost and end_pos are reduced on chip.
  */
 SDTW_API size_t sdtw_forward_workspace_bytes(const int32_t *h_query_lens, int32_t batch,

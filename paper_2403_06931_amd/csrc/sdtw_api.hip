@@ -139,23 +139,32 @@ bool fwd_flags_ok(int32_t flags) {
 
 // Persistent grid: the requested wavefronts per SIMD (default two), at most
 // one workgroup per query.
-int64_t persistent_grid_for(const Variant& v, int32_t batch, int cus, int32_t flags) {
+// Teams (of W wavefronts) in the persistent grid, and its workgroups of
+// persistent_teams(W) teams each.
+int64_t persistent_teams_for(const Variant& v, int32_t batch, int cus, int32_t flags) {
   const int wps = (flags & SDTW_F_WAVES_MASK) >> SDTW_F_WAVES_SHIFT;
   const int64_t waves_per_cu = 4LL * (wps > 0 ? wps : 2);
   return std::max<int64_t>(1, std::min<int64_t>(batch, (int64_t)cus * waves_per_cu / v.W));
 }
 
+int64_t persistent_grid_for(const Variant& v, int32_t batch, int cus, int32_t flags) {
+  const int64_t tpw = sdtw::persistent_teams(v.W);
+  return (persistent_teams_for(v, batch, cus, flags) + tpw - 1) / tpw;
+}
+
 // Row-buffer slots a forward launch of variant v needs: the plain launch
 // gives one to each query longer than one pass of the tile (64 R W rows),
 // indexed by its rank among those queries; the persistent launch one to each
-// workgroup of its grid, if any query needs a second pass.  Queries that fit
-// in one pass never touch the row buffer.
+// team of its grid (every team of every workgroup), if any query needs a
+// second pass.  Queries that fit in one pass never touch the row buffer.
 int64_t fwd_slots(const Variant& v, const int32_t* h_lens, int32_t batch, int32_t flags,
                   int cus) {
   const int64_t rows = 64LL * v.R * v.W;
   int64_t multi = 0;
   for (int32_t b = 0; b < batch; ++b) multi += h_lens[b] > rows ? 1 : 0;
-  if (flags & SDTW_F_PERSISTENT) return multi > 0 ? persistent_grid_for(v, batch, cus, flags) : 0;
+  if (flags & SDTW_F_PERSISTENT)
+    return multi > 0 ? persistent_grid_for(v, batch, cus, flags) * sdtw::persistent_teams(v.W)
+                     : 0;
   return multi;
 }
 
@@ -602,7 +611,7 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
     const int grid = (int)persistent_grid_for(v, batch, cus, flags);
     void* args[] = {(void*)&p};
     return launch(pruned ? v.pruned[1] : v.persistent[cost_kind][ck], dim3(grid),
-                  dim3(64 * v.W), args, stream);
+                  dim3(64 * v.W * sdtw::persistent_teams(v.W)), args, stream);
   }
   void* args[] = {(void*)&p};
   return launch(pruned ? v.pruned[0] : v.plain[cost_kind][ck], dim3(batch), dim3(64 * v.W),

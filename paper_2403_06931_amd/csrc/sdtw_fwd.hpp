@@ -149,6 +149,35 @@ __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
 }
 
+// Thread and wavefront index within the team of W wavefronts that works on
+// one query (a workgroup of the persistent form holds several one-wavefront
+// teams), and the team's barrier: with W = 1 every LDS exchange stays inside
+// one wavefront, whose LDS operations complete in issue order, so a fence
+// that keeps the compiler from moving them across it is enough.
+template <int W>
+__device__ __forceinline__ int team_tid() {
+  return (int)(threadIdx.x % (kWave * W));
+}
+
+template <int W>
+__device__ __forceinline__ int team_wave() {
+  return __builtin_amdgcn_readfirstlane((int)((threadIdx.x / kWave) % W));
+}
+
+template <int W>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (W == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// One-wavefront teams per workgroup of the persistent form.
+__host__ __device__ constexpr int persistent_teams(int W) { return W == 1 ? 4 : 1; }
+
 __device__ __forceinline__ int64_t uniform_i64(unsigned long long v) {
   const unsigned int hi = (unsigned int)__builtin_amdgcn_readfirstlane((int)(v >> 32));
   const unsigned int lo = (unsigned int)__builtin_amdgcn_readfirstlane((int)(v & 0xffffffffu));
@@ -421,7 +450,7 @@ template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK, ty
 __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>& L,
                                          const PassGeom& G, const V* prev_row, V* s_ref,
                                          V* s_hand, V* s_slot) {
-  const int tid = threadIdx.x;
+  const int tid = team_tid<W>();
   V rvA[T], injA[T], rvB[T], injB[T];
   step_inputs<R, T, W, KS, XL>(rvA, injA, 0, G, s_ref, s_hand, s_slot);
   for (int it = 0; it < G.nint; ++it) {
@@ -460,7 +489,7 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>&
         out_copy<T, KS>(G, it);
       }
     }
-    __syncthreads();
+    team_sync<W>();
   }
 }
 
@@ -493,7 +522,7 @@ __device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom
                                              V* s_slot) {
   using S = FwdShape<RR, T, W, KS, XL>;
   using In = typename Val<V>::In;
-  const int tid = threadIdx.x;
+  const int tid = team_tid<W>();
   G.row0 = prow0 + pos * RR;                           // first row of this lane
   G.idle = prow0 + G.wave * kWave * RR >= G.n;         // uniform: wave and lengths
   // the row above this wave's first row, if it is a row checkpoint
@@ -544,7 +573,7 @@ __device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom
   for (int e = tid; e < W * S::SH * T; e += S::THREADS) s_hand[e] = Val<V>::inf();
   for (int e = tid; e < S::SLOTS; e += S::THREADS) s_slot[e] = Val<V>::inf();
   for (int e = tid; e < S::SR * T; e += S::THREADS) s_ref[e] = Val<V>::zero();
-  __syncthreads();
+  team_sync<W>();
   {
     Stager<RR, T, W, KS, XL, V> st0, st1;
     st0.load(p.reference, p.ref_len, prev_row, G.ntiles * T, 0, tid);
@@ -552,7 +581,7 @@ __device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom
     st0.commit(s_ref, s_hand, 0, tid);
     st1.commit(s_ref, s_hand, KS, tid);
   }
-  __syncthreads();
+  team_sync<W>();
 
   if (G.wave == out_wave) {
     fwd_pass_out<0, RR, T, W, KS, XL, KIND, CKPT, V>(out_k, p, L, G, prev_row, s_ref, s_hand,
@@ -600,10 +629,10 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   V* s_hand = s_ref + S0::SR * T;
   V* s_slot = s_hand + W * S0::SH * T;
   using S = FwdShape<R, T, W, KS, XL>;
-  const int tid = threadIdx.x;
+  const int tid = team_tid<W>();
   PassGeom G;
   G.lane = tid & (kWave - 1);
-  G.wave = wave_id();
+  G.wave = team_wave<W>();
   const int pos = G.wave * kWave + G.lane;             // lane position in the team
   G.n = __builtin_amdgcn_readfirstlane(p.lens[b]);     // uniform: loop bounds below
   G.qoff = qoff;
@@ -687,6 +716,17 @@ __device__ __forceinline__ int64_t query_offset(const FwdParams& p, int b) {
   return query_pos(p, b, 0x7fffffff).off;
 }
 
+// The same for a one-wavefront team that shares its workgroup with others:
+// a wavefront sum, no LDS and no workgroup barrier.
+__device__ __forceinline__ int64_t wave_query_offset(const FwdParams& p, int b) {
+  if (p.offsets != nullptr) return p.offsets[b];
+  unsigned long long acc = 0;
+  for (int k = (int)(threadIdx.x & (kWave - 1)); k < b; k += kWave)
+    acc += (unsigned long long)p.lens[k];
+  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  return uniform_i64(acc);
+}
+
 // One workgroup per query; a query longer than one pass owns the row-buffer
 // slot of its rank among such queries.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
@@ -722,34 +762,48 @@ __global__ __launch_bounds__(kWave * W) void sdtw_fwd_u8_kernel(const FwdParams 
   fwd_query<R, T, W, KS, XL, kSquared, false, Code8>(p, b, query_offset(p, b), row, s_mem);
 }
 
-// Persistent form: a fixed grid pops queries (in the given order, longest
-// first) from a device counter; each workgroup owns one row-buffer slot
-// (for queries that need several passes).  Every workgroup leaves
-// the loop once the counter passes the batch size.
+// Persistent form: a fixed grid of teams pops queries (in the given order,
+// longest first) from a device counter; each team owns one row-buffer slot
+// (for queries that need several passes) and its own LDS.  A workgroup
+// holds persistent_teams(W) teams: four independent one-wavefront teams for
+// W = 1 (a grid of one-wavefront workgroups was placed unevenly on the
+// SIMDs), else one.  Every team leaves the loop once the counter passes
+// the batch size.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
-__global__ __launch_bounds__(kWave * W) void sdtw_fwd_persistent_kernel(const FwdParams p) {
+__global__ __launch_bounds__(kWave * W * persistent_teams(W)) void sdtw_fwd_persistent_kernel(
+    const FwdParams p) {
   using S = FwdShape<R, T, W, KS, XL>;
-  __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
+  constexpr int TEAMS = persistent_teams(W);
+  __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS * TEAMS];
   __shared__ int s_item;
-  float* row = p.rowbuf + (int64_t)blockIdx.x * p.row_stride;
-  // Wave 0 pops the next item: every lane takes part in the atomic (lane 0
-  // adds 1, the others 0) so there is no lane-dependent branch; the value is
-  // broadcast through LDS.  The item is made wave-uniform with
-  // readfirstlane, so the loop, which holds barriers, has a uniform exit.
+  const int team = TEAMS > 1 ? wave_id() : 0;
+  float* row = p.rowbuf + ((int64_t)blockIdx.x * TEAMS + team) * p.row_stride;
+  float* mem = s_mem + team * S::LDS_FLOATS;
+  // The team's wave 0 pops the next item: every lane takes part in the
+  // atomic (lane 0 adds 1, the others 0) so there is no lane-dependent
+  // branch; with several waves the value is broadcast through LDS.  The
+  // item is made wave-uniform with readfirstlane, so the loop, which holds
+  // barriers, has a uniform exit.
   const int lane = threadIdx.x & (kWave - 1);
   for (;;) {
-    if (wave_id() == 0) {
-      const int old = atomicAdd(p.queue, lane == 0 ? 1 : 0);
-      s_item = __builtin_amdgcn_readfirstlane(old);
+    int item;
+    if constexpr (W == 1) {
+      item = __builtin_amdgcn_readfirstlane(atomicAdd(p.queue, lane == 0 ? 1 : 0));
+    } else {
+      if (wave_id() == 0) {
+        const int old = atomicAdd(p.queue, lane == 0 ? 1 : 0);
+        s_item = __builtin_amdgcn_readfirstlane(old);
+      }
+      __syncthreads();
+      item = __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();
     }
-    __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
     if (item >= p.batch) break;
     const int b = __builtin_amdgcn_readfirstlane(p.order[item]);
+    const int64_t off = TEAMS > 1 ? wave_query_offset(p, b) : query_offset(p, b);
     // a query's last pass may hold fewer rows per lane (not with checkpoints)
     fwd_query<R, T, W, KS, XL, KIND, CKPT, float, CKPT ? R : tail_rows_min<R>()>(
-        p, b, query_offset(p, b), row, s_mem);
+        p, b, off, row, mem);
   }
 }
 
