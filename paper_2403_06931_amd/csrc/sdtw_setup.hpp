@@ -52,25 +52,39 @@ __global__ __launch_bounds__(kScanThreads) void sdtw_offsets_kernel(
   if (tid == kScanThreads - 1) offsets[batch] = s_sum[tid];
 }
 
-// Processing order for the persistent form: queries sorted by the number
-// of row passes they need (most first), so the longest work starts first and
-// the short queries fill the tail.  Queries with equal pass counts are
-// placed in an unspecified order; results do not depend on the order.  Also
-// zeroes the work counter (a kernel, not a memset, so the sequence is safe to
-// capture in a graph and replay).
+// Processing order for the persistent form: queries sorted by their work
+// (most first), so the longest work starts first and the short queries fill
+// the tail.  Work is counted in quarter passes: the full passes, then the
+// last pass in the form the kernel runs it, a quarter or a half pass when
+// its rows fit and the tile has that form (min_quarters = 1, 2 or 4: the
+// smallest it has), else a whole pass.  (Counting the last pass as whole
+// left the simulated makespan of the 4,096 x U{250..4,000} batch 8.6 %
+// above the balanced one, against 2.9 % this way.)  Queries with equal
+// work are placed in an unspecified order; results do not depend on the
+// order.  Also zeroes the work counter (a kernel, not a memset, so the
+// sequence is safe to capture in a graph and replay).
 constexpr int kOrderBins = 4096;
+
+__device__ __forceinline__ int order_key(int n, int rows, int min_quarters) {
+  const int full = n > 0 ? (n - 1) / rows : 0;
+  const int left = n - full * rows;
+  int last = 4;
+  if (min_quarters <= 2 && left <= rows / 2) last = 2;
+  if (min_quarters <= 1 && left <= rows / 4) last = 1;
+  return min(kOrderBins - 1, 4 * full + last);
+}
 
 __global__ __launch_bounds__(kScanThreads) void sdtw_order_kernel(
     const int32_t* __restrict__ lens, int32_t batch, int32_t rows_per_pass,
-    int32_t* __restrict__ order, int32_t* __restrict__ queue) {
+    int32_t min_quarters, int32_t* __restrict__ order, int32_t* __restrict__ queue) {
   __shared__ int32_t s_cnt[kOrderBins];
   const int tid = threadIdx.x;
   for (int i = tid; i < kOrderBins; i += kScanThreads) s_cnt[i] = 0;
   if (tid == 0) queue[0] = 0;
   __syncthreads();
   for (int b = tid; b < batch; b += kScanThreads) {
-    const int passes = min(kOrderBins - 1, (lens[b] + rows_per_pass - 1) / rows_per_pass);
-    atomicAdd(&s_cnt[kOrderBins - 1 - passes], 1);     // descending by passes
+    const int key = order_key(lens[b], rows_per_pass, min_quarters);
+    atomicAdd(&s_cnt[kOrderBins - 1 - key], 1);        // descending by work
   }
   __syncthreads();
   if (tid == 0) {
@@ -83,8 +97,8 @@ __global__ __launch_bounds__(kScanThreads) void sdtw_order_kernel(
   }
   __syncthreads();
   for (int b = tid; b < batch; b += kScanThreads) {
-    const int passes = min(kOrderBins - 1, (lens[b] + rows_per_pass - 1) / rows_per_pass);
-    const int at = atomicAdd(&s_cnt[kOrderBins - 1 - passes], 1);
+    const int key = order_key(lens[b], rows_per_pass, min_quarters);
+    const int at = atomicAdd(&s_cnt[kOrderBins - 1 - key], 1);
     order[at] = b;
   }
 }
