@@ -604,8 +604,8 @@ int forward_impl(const float* queries, const int32_t* h_query_lens, const int32_
     int32_t* queue = reinterpret_cast<int32_t*>(ws + L.queue);
     int32_t rows = 64 * v.R * v.W;
     // the smallest last pass the kernel runs, in quarter passes (its tail
-    // forms: R/4 rows per lane from R = 8, R/2 from R = 4; none with
-    // checkpoints)
+    // forms: R/4, R/2 and 3R/4 rows per lane from R = 8, R/2 from R = 4;
+    // none with checkpoints)
     int32_t min_quarters = ck ? 4 : (v.R >= 8 ? 1 : (v.R >= 4 ? 2 : 4));
     void* oargs[] = {(void*)&query_lens, (void*)&batch, (void*)&rows, (void*)&min_quarters,
                      (void*)&order, (void*)&queue};

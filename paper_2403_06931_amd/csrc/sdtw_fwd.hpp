@@ -615,9 +615,9 @@ constexpr int tail_rows_min() {
 // waves of this workgroup and store cost and end position.  `row` is the
 // row-buffer slot (rows carried from one pass to the next, as V words).
 // Full passes hold R rows per lane.  With RT < R the last pass, when its
-// rows fit, holds R/2 or (if RT allows) R/4 rows per lane instead: fewer
-// padding rows below row N for a query that is not a multiple of a pass
-// long, at a somewhat higher cost per cell.
+// rows fit, holds R/2 or (if RT allows) R/4 or 3R/4 rows per lane instead,
+// the fewest that hold them: fewer padding rows below row N for a query
+// that is not a multiple of a pass long, at a somewhat higher cost per cell.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, typename V = float,
           int RT = R>
 __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qoff,
@@ -669,6 +669,14 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
         fwd_one_pass<R / 2, T, W, KS, XL, KIND, CKPT, V>(p, b, G, pos, prow0, left, true, q, q2,
                                                          prev_row, s_ref, s_hand, s_slot);
         continue;
+      }
+      if constexpr (RT <= R / 4) {
+        if (last_pass && left <= kWave * W * (3 * R / 4)) {
+          fwd_one_pass<3 * R / 4, T, W, KS, XL, KIND, CKPT, V>(p, b, G, pos, prow0, left, true,
+                                                               q, q2, prev_row, s_ref, s_hand,
+                                                               s_slot);
+          continue;
+        }
       }
     }
     fwd_one_pass<R, T, W, KS, XL, KIND, CKPT, V>(p, b, G, pos, prow0, S::ROWS, last_pass, q, q2,

@@ -55,13 +55,13 @@ __global__ __launch_bounds__(kScanThreads) void sdtw_offsets_kernel(
 // Processing order for the persistent form: queries sorted by their work
 // (most first), so the longest work starts first and the short queries fill
 // the tail.  Work is counted in quarter passes: the full passes, then the
-// last pass in the form the kernel runs it, a quarter or a half pass when
-// its rows fit and the tile has that form (min_quarters = 1, 2 or 4: the
-// smallest it has), else a whole pass.  (Counting the last pass as whole
-// left the simulated makespan of the 4,096 x U{250..4,000} batch 8.6 %
-// above the balanced one, against 2.9 % this way.)  Queries with equal
-// work are placed in an unspecified order; results do not depend on the
-// order.  Also zeroes the work counter (a kernel, not a memset, so the
+// last pass in the form the kernel runs it, a quarter, half or
+// three-quarter pass when its rows fit and the tile has that form
+// (min_quarters = 1: all three, 2: the half pass only, 4: none), else a
+// whole pass.  (Counting every last pass as a whole one left the modelled
+// makespan of the 4,096 x U{250..4,000} batch 8.6 % above the balanced one,
+// against 2-3 % this way.)  Queries with equal work are placed in an
+// unspecified order; results do not depend on the order.  Also zeroes the work counter (a kernel, not a memset, so the
 // sequence is safe to capture in a graph and replay).
 constexpr int kOrderBins = 4096;
 
@@ -69,6 +69,7 @@ __device__ __forceinline__ int order_key(int n, int rows, int min_quarters) {
   const int full = n > 0 ? (n - 1) / rows : 0;
   const int left = n - full * rows;
   int last = 4;
+  if (min_quarters <= 1 && left <= 3 * rows / 4) last = 3;
   if (min_quarters <= 2 && left <= rows / 2) last = 2;
   if (min_quarters <= 1 && left <= rows / 4) last = 1;
   return min(kOrderBins - 1, 4 * full + last);
