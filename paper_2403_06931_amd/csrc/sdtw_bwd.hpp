@@ -652,41 +652,59 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
 // a query's span [path_lo, end_pos] are loaded (the others were never
 // written) and the rest read as +0; the running sum starts at +0 and is
 // never -0, so adding +0 leaves it unchanged and the result equals the sum
-// over covering queries only.  The next kRefReduceBatch queries' entries
-// are loaded while the current ones are added.
+// over covering queries only.  Queries go 64 at a time: each wavefront
+// loads their spans with one vector load per bound (one query per lane) and
+// reads them back with readlane, and loads the next 64 queries' entries
+// while it adds the current ones.
 constexpr int kRefReduceThreads = 256;
-constexpr int kRefReduceBatch = 64;
+constexpr int kRefReduceBatch = kWave;
 
-__device__ __forceinline__ float ref_part_at(const float* __restrict__ ref_part,
-                                             int64_t part_stride, const int32_t* __restrict__ lo,
-                                             const int64_t* __restrict__ hi, int32_t batch, int b,
-                                             int j) {
-  return b < batch && j >= lo[b] && j <= (int)hi[b] ? ref_part[(int64_t)b * part_stride + j]
-                                                    : 0.0f;
+struct RefSpans {
+  int lo, hi;           // span of query b0 + lane (empty past the batch)
+
+  __device__ __forceinline__ void load(const int32_t* __restrict__ path_lo,
+                                       const int64_t* __restrict__ end_pos, int32_t batch,
+                                       int b0, int lane) {
+    const int b = b0 + lane;
+    lo = b < batch ? path_lo[b] : 1;
+    hi = b < batch ? (int)end_pos[b] : 0;
+  }
+};
+
+__device__ __forceinline__ void ref_part_batch(const float* __restrict__ ref_part,
+                                               int64_t part_stride, const RefSpans& sp, int b0,
+                                               int j, float (&v)[kRefReduceBatch]) {
+#pragma unroll
+  for (int u = 0; u < kRefReduceBatch; ++u) {
+    const int l = __builtin_amdgcn_readlane(sp.lo, u);
+    const int h = __builtin_amdgcn_readlane(sp.hi, u);
+    v[u] = j >= l && j <= h ? ref_part[(int64_t)(b0 + u) * part_stride + j] : 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(kRefReduceThreads) void sdtw_ref_reduce_kernel(
     const float* __restrict__ ref_part, int64_t part_stride, const int32_t* __restrict__ lo,
     const int64_t* __restrict__ hi, int32_t batch, int32_t ref_len, float* __restrict__ grad_ref) {
+  const int lane = threadIdx.x & (kWave - 1);
   const int j = blockIdx.x * kRefReduceThreads + threadIdx.x;
-  if (j >= ref_len) return;
+  // (lanes past ref_len stay in the loop, whose bounds are uniform, and
+  // load nothing: no span reaches them)
   float acc = 0.0f;
   float v[kRefReduceBatch], nv[kRefReduceBatch];
-#pragma unroll
-  for (int u = 0; u < kRefReduceBatch; ++u)
-    nv[u] = ref_part_at(ref_part, part_stride, lo, hi, batch, u, j);
+  RefSpans sp;
+  sp.load(lo, hi, batch, 0, lane);
+  ref_part_batch(ref_part, part_stride, sp, 0, j, nv);
   for (int b = 0; b < batch; b += kRefReduceBatch) {
 #pragma unroll
     for (int u = 0; u < kRefReduceBatch; ++u) v[u] = nv[u];
     if (b + kRefReduceBatch < batch) {
-#pragma unroll
-      for (int u = 0; u < kRefReduceBatch; ++u)
-        nv[u] = ref_part_at(ref_part, part_stride, lo, hi, batch, b + kRefReduceBatch + u, j);
+      sp.load(lo, hi, batch, b + kRefReduceBatch, lane);
+      ref_part_batch(ref_part, part_stride, sp, b + kRefReduceBatch, j, nv);
     }
 #pragma unroll
     for (int u = 0; u < kRefReduceBatch; ++u) acc = acc + v[u];
   }
-  grad_ref[j] = acc;
+  if (j < ref_len) grad_ref[j] = acc;
 }
 
 }  // namespace sdtw
