@@ -346,7 +346,7 @@ struct CodeChunk {
 };
 
 // Follow the direction codes of round r's blocks of query b.  One wavefront;
-// every lane runs the same (uniform) walk and lane 0 stores.  Code rows are
+// every lane runs the same (uniform) walk.  Code rows are
 // staged through LDS (`chunk`, 64 rows) 64 at a time: within a segment the
 // code row g = i - 1 + (lane owning column j) never increases along the
 // walk, and falls by at most 2 per move, so the chunk below the current one
@@ -378,8 +378,8 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
       while (j >= cs) {
         const int L = (j - cs) >> 4;
         const int c = (j - cs) & (kDirCols - 1);
-        const int g = i - 1 + L;
-        const int k = g / kWalkChunk;
+        const int g = i - 1 + L;                // >= 0: i >= 1, L >= 0
+        const int k = (int)((unsigned)g / kWalkChunk);
         if (k != kc) {
           if (kp != k) pre.fetch(seg, rs, k, code_rows, lane);
           __builtin_amdgcn_wave_barrier();
@@ -390,7 +390,7 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
           if (k > 0) pre.fetch(seg, rs, k - 1, code_rows, lane);
         }
         const uint32_t w =
-            (uint32_t)wave_uniform((int)chunk[(g - k * kWalkChunk) * kWave + L]);
+            (uint32_t)wave_uniform((int)chunk[((unsigned)g % kWalkChunk) * kWave + L]);
         // pass through the cells c, c-1, ... of this word whose code is
         // "left" (cell c' is bit pair 15-c'); the first other one ends the
         // run in this row
@@ -403,19 +403,19 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
         }
         const int bit = __builtin_ctz(stop);    // 2(15-c') for the cell c' that stops
         j -= (bit >> 1) - pc;
+        // (every lane stores the same value to the same address: one write,
+        // and no lane mask to set up and restore around it)
         if (i == 1) {                           // the start cell
-          if (lane == 0) {
-            rlo[1] = j;
-            p.path_lo[b] = j;
-          }
+          rlo[1] = j;
+          p.path_lo[b] = j;
           done = 1;
           break;
         }
         const bool diagonal = ((w >> (bit + 1)) & 1u) == 0;
-        if (lane == 0) rlo[i] = j;
+        rlo[i] = j;
         i -= 1;
         if (diagonal) j -= 1;
-        if (lane == 0) rhi[i] = j;
+        rhi[i] = j;
       }
     }
   }
