@@ -321,9 +321,10 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
   }
 }
 
-// Code rows [64k, 64k + 64) of a segment (rs words apart) staged as 4096
-// consecutive words; each lane holds 16 uint4 of them.  Rows past the
-// segment's end read as zero (they are never addressed).
+// Code rows [kWalkChunk * k, kWalkChunk * (k + 1)) of a segment (rs words
+// apart) staged as kWalkChunk * 64 consecutive words; each lane holds
+// kWalkChunk / 4 uint4 of them.  Rows past the segment's end read as zero
+// (they are never addressed).
 struct CodeChunk {
   uint4 v[kWalkChunk * kWave / (4 * kWave)];
 
@@ -346,11 +347,11 @@ struct CodeChunk {
 };
 
 // Follow the direction codes of round r's blocks of query b.  One wavefront;
-// every lane runs the same (uniform) walk.  Code rows are
-// staged through LDS (`chunk`, 64 rows) 64 at a time: within a segment the
-// code row g = i - 1 + (lane owning column j) never increases along the
-// walk, and falls by at most 2 per move, so the chunk below the current one
-// is always the next one needed and is fetched ahead.
+// every lane runs the same (uniform) walk.  Code rows are staged through LDS
+// (`chunk`, kWalkChunk rows) kWalkChunk at a time: within a segment the code
+// row g = i - 1 + (lane owning column j) never increases along the walk, so
+// the chunk below the current one is always the next one needed and is
+// fetched ahead.
 __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uint32_t* chunk) {
   const int lane = threadIdx.x & (kWave - 1);
   if (wave_uniform(p.state[4 * b + 2]) != 0) return;
@@ -398,7 +399,21 @@ __device__ __forceinline__ void walk_query(const BwdParams& p, int r, int b, uin
         const int pc = kDirCols - 1 - c;
         const uint32_t stop = ~is_left & 0x55555555u & (~0u << (2 * pc));
         if (stop == 0) {
-          j -= c + 1;                           // into the previous lane's columns
+          // The rest of this word is "left", so the run goes on in the words
+          // of lanes L-1, L-2, ... of row i, which sit on a diagonal of the
+          // staged rows (lane x's word at code row g - (L - x)).  Every lane
+          // x in [xlo, L) whose word is in this chunk tests its own word at
+          // once; a ballot finds the right-most one holding a cell that is
+          // not "left", and the walk continues at that word's last column,
+          // or below the chunk if there is none.
+          const int d0 = g - kc * kWalkChunk;   // chunk row of the current word
+          const int xlo = L > d0 ? L - d0 : 0;
+          const bool mine = lane >= xlo && lane < L;
+          const uint32_t wx = chunk[(mine ? d0 - L + lane : 0) * kWave + lane];
+          const bool stops = mine && (((wx >> 1) & wx & 0x55555555u) != 0x55555555u);
+          const unsigned long long m = __ballot(stops);
+          j = m != 0 ? cs + kDirCols * (kWave - 1 - __clzll(m)) + (kDirCols - 1)
+                     : cs + kDirCols * xlo - 1;
           continue;
         }
         const int bit = __builtin_ctz(stop);    // 2(15-c') for the cell c' that stops
