@@ -267,11 +267,16 @@ __device__ __forceinline__ void rowck_copy(const FwdParams& p, const PassGeom& G
   }
 }
 
+// Checkpoint handling inside the step loop: none, capture the checkpoint
+// column with selects (stored at the interval's end), or store it in the
+// step that reaches it (checkpoints closer than one barrier interval).
+enum CkptMode { kCkNone = 0, kCkSelect = 1, kCkEachStep = 2 };
+
 // One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
 // the wavefront holding the row to store and that row's register index.
 // `top` is the block's top boundary: the previous lane's bottom row over this
 // tile (for lane 0, the previous wave's, or the top boundary of the pass).
-template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK, typename V>
+template <int R, int T, int W, int KS, int XL, int KIND, int CKM, int OUTK, typename V>
 __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>& L,
                                          const PassGeom& G, const V (&rv)[T],
                                          const V (&top)[T], int g, V* s_hand, V* s_slot) {
@@ -373,19 +378,15 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
     for (int t = 0; t < T; ++t) hout[t] = L.bot[t];
   }
 
-  if constexpr (CKPT) {
-    // Checkpoint column kc*ckpt_every - 1 is the last column of tile
-    // kc*tpc - 1 (tpc = tiles per checkpoint; ckpt_every is a multiple of T),
-    // which the lane reaches at step my_delay + kc*tpc - 1.  The lane's rows
-    // there are captured with selects and stored at the interval's end, or
-    // right away when checkpoints come closer than one interval apart.
-    if (G.ck_each_step) {
-      if (g == L.ck_h) ckpt_store(p, L, G, L.dl);
-    } else {
-      const bool hit = g == L.ck_h;
+  // Checkpoint column kc*ckpt_every - 1 is the last column of tile kc*tpc - 1
+  // (tpc = tiles per checkpoint; ckpt_every is a multiple of T), which the
+  // lane reaches at step my_delay + kc*tpc - 1.
+  if constexpr (CKM == kCkEachStep) {
+    if (g == L.ck_h) ckpt_store(p, L, G, L.dl);
+  } else if constexpr (CKM == kCkSelect) {
+    const bool hit = g == L.ck_h;
 #pragma unroll
-      for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
-    }
+    for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
   }
 }
 
@@ -443,9 +444,25 @@ __device__ __forceinline__ void out_copy(const PassGeom& G, int it) {
   }
 }
 
-// All barrier intervals of one pass.  The reference tile of step g+1 (and,
-// without XL, its handoff input) is read while step g computes (two register
-// sets, the step loop unrolled by two).
+// The KS steps of barrier interval `it`.  The reference tile of step g+1
+// (and, without XL, its handoff input) is read while step g computes (two
+// register sets, the step loop unrolled by two).
+template <int R, int T, int W, int KS, int XL, int KIND, int CKM, int OUTK, typename V>
+__device__ __forceinline__ void fwd_steps(const FwdParams& p, LaneState<R, T, V>& L,
+                                          const PassGeom& G, int it, V (&rvA)[T], V (&injA)[T],
+                                          V (&rvB)[T], V (&injB)[T], const V* s_ref, V* s_hand,
+                                          V* s_slot) {
+#pragma unroll 1
+  for (int s = 0; s < KS; s += 2) {
+    const int g = it * KS + s;
+    step_inputs<R, T, W, KS, XL>(rvB, injB, g + 1, G, s_ref, s_hand, s_slot);
+    fwd_step<R, T, W, KS, XL, KIND, CKM, OUTK, V>(p, L, G, rvA, injA, g, s_hand, s_slot);
+    step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
+    fwd_step<R, T, W, KS, XL, KIND, CKM, OUTK, V>(p, L, G, rvB, injB, g + 1, s_hand, s_slot);
+  }
+}
+
+// All barrier intervals of one pass.
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT, int OUTK, typename V>
 __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>& L,
                                          const PassGeom& G, const V* prev_row, V* s_ref,
@@ -460,15 +477,19 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>&
     // does not fill it) computes nothing: nothing flows upward, so its cells
     // are never read.  It still stages its share of the reference and meets
     // every barrier; its issue slots go to the other waves on its SIMD.
+    // (the checkpoint mode is a loop-invariant choice, taken outside the
+    // step loop so that the loop holds only the chosen form's instructions)
     if (!G.idle) {
-#pragma unroll 1
-      for (int s = 0; s < KS; s += 2) {
-        const int g = it * KS + s;
-        step_inputs<R, T, W, KS, XL>(rvB, injB, g + 1, G, s_ref, s_hand, s_slot);
-        fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvA, injA, g, s_hand, s_slot);
-        step_inputs<R, T, W, KS, XL>(rvA, injA, g + 2, G, s_ref, s_hand, s_slot);
-        fwd_step<R, T, W, KS, XL, KIND, CKPT, OUTK, V>(p, L, G, rvB, injB, g + 1, s_hand,
-                                                       s_slot);
+      if constexpr (CKPT) {
+        if (G.ck_each_step)
+          fwd_steps<R, T, W, KS, XL, KIND, kCkEachStep, OUTK, V>(p, L, G, it, rvA, injA, rvB,
+                                                                 injB, s_ref, s_hand, s_slot);
+        else
+          fwd_steps<R, T, W, KS, XL, KIND, kCkSelect, OUTK, V>(p, L, G, it, rvA, injA, rvB, injB,
+                                                               s_ref, s_hand, s_slot);
+      } else {
+        fwd_steps<R, T, W, KS, XL, KIND, kCkNone, OUTK, V>(p, L, G, it, rvA, injA, rvB, injB,
+                                                           s_ref, s_hand, s_slot);
       }
     }
     // The stager's commit waits for its loads with a vmcnt wait, which on
