@@ -123,23 +123,24 @@ SDTW_API size_t sdtw_forward_workspace_bytes(const int32_t *h_query_lens, int32_
 SDTW_API size_t sdtw_workspace_bytes(const int32_t *h_query_lens, int32_t batch,
                                      int64_t ref_len, int32_t flags, int32_t ckpt_every);
 
-/* Row-checkpoint spacing: the forward also stores D(k*512, 1..ref_len) for
- * every k >= 1 with k*512 < len_b, so that the backward can recompute a
- * block of columns as independent bands of 512 rows. */
-#define SDTW_ROW_CKPT_EVERY 512
+/* Row-checkpoint spacing: the forward also stores D(k*256, 1..ref_len) for
+ * every k >= 1 with k*256 < len_b, so that the backward can recompute a
+ * block of columns as independent bands of 256 rows (or of a multiple of
+ * 256 rows). */
+#define SDTW_ROW_CKPT_EVERY 256
 
 /*
  * Number of float32 entries of the checkpoint buffer for this batch and
- * checkpoint interval: n_ckpt * T + floor(T / 512) * ref_len, where
+ * checkpoint interval: n_ckpt * T + floor(T / 256) * ref_len, where
  * T = sum_b len_b and n_ckpt = ceil(ref_len / ckpt_every) - 1.
  * Layout, columns (Eq. (1)'s D over whole columns): query b's block starts
  * at offset(b) * n_ckpt (offset(b) = sum of the lengths of queries 0..b-1)
  * and holds n_ckpt columns of len_b values each; column k (k = 1..n_ckpt)
  * is D(1..len_b, k*ckpt_every), i.e. the DP column of 0-based reference
  * index k*ckpt_every - 1.
- * Then rows, from entry n_ckpt * T on: row r = floor(offset(b) / 512) + k - 1
- * of ref_len values is D(k*512, 1..ref_len) of query b, for k >= 1 and
- * k*512 < len_b (rows of different queries never coincide; rows no query
+ * Then rows, from entry n_ckpt * T on: row r = floor(offset(b) / 256) + k - 1
+ * of ref_len values is D(k*256, 1..ref_len) of query b, for k >= 1 and
+ * k*256 < len_b (rows of different queries never coincide; rows no query
  * owns are left untouched).
  * Returns 0 if no checkpoint is needed (ref_len <= ckpt_every) or on invalid
  * arguments.

@@ -31,7 +31,7 @@ def SDTW_F_WAVES_PER_SIMD(n: int) -> int:
 
 SDTW_MAX_REF_LEN = 1 << 30
 SDTW_NOALLOC_SCRATCH_BYTES = 16 << 20
-SDTW_ROW_CKPT_EVERY = 512
+SDTW_ROW_CKPT_EVERY = 256
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p

@@ -269,6 +269,12 @@ constexpr size_t kBwdCodeBudget = size_t(2) << 30;
 // walk ends) are bound by issue slots, where bands would only add pipeline
 // fill and more wavefronts beside the walkers: whole blocks there.
 constexpr int kFirstBandedKernel = 1;
+// Band height, a multiple of the row-checkpoint spacing.  (Bands of 512
+// rows in the first banded kernel and 256 after it measured 1.58 ms per
+// backward on workload 4, 512 throughout 1.61-1.62 ms, 256 throughout
+// 1.52 ms: the shorter latency outweighs the extra pipeline fill.)
+constexpr int kBandRows = 256;
+static_assert(kBandRows % sdtw::kRowCkpt == 0, "bands start on row checkpoints");
 
 struct BwdLayout {
   size_t offsets, state, lo, row_lo, row_hi, part, codes, total;
@@ -377,6 +383,7 @@ sdtw::BwdParams bwd_params(const float* queries, const int32_t* query_lens, int3
   p.max_rows = nmax;
   p.round = 0;
   p.nband = 1;
+  p.band_rows = sdtw::kRowCkpt;
   p.code_half = L.code_half;
   return p;
 }
@@ -408,8 +415,10 @@ int bwd_walk(sdtw::BwdParams& p, const BwdLayout& L, const int32_t* query_lens, 
   const int round_wpg = (int)std::max<size_t>(1, std::min<size_t>(4, 65536 / round_lds));
   // Row bands: later rounds' blocks (few queries still walking, so bound by
   // one block's latency rather than by issue slots) are recomputed as
-  // bands of kRowCkpt rows from the forward's row checkpoints.
-  const int32_t nband = p.rowck != nullptr ? (nmax + sdtw::kRowCkpt - 1) / sdtw::kRowCkpt : 1;
+  // bands from the forward's row checkpoints.
+  auto bands = [&](int rows) -> int32_t {
+    return p.rowck != nullptr ? (nmax + rows - 1) / rows : 1;
+  };
   {
     const void* dirs = sq ? reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<0>)
                           : reinterpret_cast<const void*>(&sdtw::sdtw_bwd_dirs_kernel<1>);
@@ -429,7 +438,8 @@ int bwd_walk(sdtw::BwdParams& p, const BwdLayout& L, const int32_t* query_lens, 
   for (int r = 0; r < L.rounds; ++r) {
     p.round = r;
     // (no next round: no recompute wavefronts, padding ones included)
-    p.nband = r + 1 == L.rounds ? 0 : (r >= kFirstBandedKernel ? nband : 1);
+    p.band_rows = kBandRows;
+    p.nband = r + 1 == L.rounds ? 0 : (r >= kFirstBandedKernel ? bands(p.band_rows) : 1);
     const int64_t grid = (int64_t)batch * (1 + (int64_t)L.slots * p.nband);
     void* args[] = {(void*)&p};
     if (hipLaunchKernel(round_fn, dim3((unsigned)((grid + round_wpg - 1) / round_wpg)),

@@ -93,6 +93,7 @@ struct BwdParams {
   int32_t round;
   int32_t nband;              // row bands per recomputed block (1: the whole block;
                               // 0 in a round kernel with no round after it)
+  int32_t band_rows;          // rows of a band (a multiple of kRowCkpt) when nband > 1
   int64_t code_half;          // words of one code buffer (two alternate by round)
 };
 
@@ -208,9 +209,9 @@ __device__ __forceinline__ void dirs_step(int g, int lane, int nrows, float il, 
 // walker's current row as last stored, which only decreases, so any value
 // read is enough; lowered further by the block's right checkpoint column)
 // and store its direction codes.  With p.nband > 1 the block is split into
-// bands of kRowCkpt rows, each recomputed on its own from the forward's row
-// checkpoint above it; this call takes band z.  One wavefront; LDS `dyn`:
-// query values and the left boundary column, 2 * max_rows floats.
+// bands of p.band_rows rows, each recomputed on its own from the forward's
+// row checkpoint above it; this call takes band z.  One wavefront; LDS
+// `dyn`: query values and the left boundary column, 2 * max_rows floats.
 template <int KIND>
 __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int t, int z,
                                            float* dyn) {
@@ -240,10 +241,10 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
     nrows = wave_uniform(last);
     if (nrows == 0) return;                    // the path does not reach this block
   }
-  // band z: rows r0+1 .. r0+brows
-  const int r0 = z * kRowCkpt;
+  // band z: rows r0+1 .. r0+brows (r0 a multiple of kRowCkpt)
+  const int r0 = z * p.band_rows;
   if (r0 >= nrows) return;
-  const int brows = p.nband > 1 && r0 + kRowCkpt < nrows ? kRowCkpt : nrows - r0;
+  const int brows = p.nband > 1 && r0 + p.band_rows < nrows ? p.band_rows : nrows - r0;
   float* lq = dyn;
   float* ledge = dyn + p.max_rows;
   const float* __restrict__ q = p.queries + qoff + r0;
@@ -258,7 +259,7 @@ __device__ __forceinline__ void dirs_block(const BwdParams& p, int r, int b, int
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // the band's top boundary: row r0 (row 0 = zeros for the first band)
   const float* top =
-      r0 > 0 ? p.rowck + (qoff / kRowCkpt + z - 1) * (int64_t)p.ref_len : nullptr;
+      r0 > 0 ? p.rowck + (qoff / kRowCkpt + r0 / kRowCkpt - 1) * (int64_t)p.ref_len : nullptr;
 
   const int bc0 = blk * K;
   const int bend = bc0 + K < p.ref_len ? bc0 + K : p.ref_len;

@@ -15,7 +15,7 @@
 namespace sdtw {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kRowCkpt = 512;        // row checkpoints: D(512k, 1..M) for 512k < N
+constexpr int kRowCkpt = 256;        // row checkpoints: D(256k, 1..M) for 256k < N
 constexpr int kSquared = 0;
 constexpr int kAbsolute = 1;
 // Squared difference with early pruning (the paper's Section 8 proposal):

@@ -209,6 +209,7 @@ struct PassGeom {
   bool final_pass;                           // the stored row is row N
   bool idle;                                 // every row of this wave is past row N
   float* rowck;                              // row checkpoint this wave copies, or nullptr
+  float* rowck_mid;                          // row checkpoint inside this wave, or nullptr
   int64_t qoff;
   float* row;                                // row-buffer slot of the query
   float* s_out;                              // LDS: row N over one interval
@@ -239,13 +240,15 @@ __device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& 
 }
 
 // Row checkpoints D(kRowCkpt*k, 1..M) for every multiple of kRowCkpt below
-// N.  Such a row is always a bottom row handed over through a handoff ring:
-// kRowCkpt is a multiple of 64*R for every R (and R/2, R/4), so within a
-// pass it is the bottom row of a wavefront, or else the last row of a pass,
-// which the next pass stages into wavefront 0's ring.  The wavefront whose
-// ring carries it copies the tiles it read in barrier interval `it` to
-// global memory at the interval's end (a tile stays in the ring for two
-// more intervals after its read).  Checkpoint stores are non-temporal: the
+// N.  With checkpoints every pass holds R rows per lane.  For R = 2 and 4,
+// kRowCkpt is a multiple of a wavefront's 64*R rows, so such a row is the
+// bottom row of a wavefront, or else the last row of a pass, which the next
+// pass stages into wavefront 0's ring: the wavefront whose ring carries it
+// copies the tiles it read in barrier interval `it` to global memory at the
+// interval's end (a tile stays in the ring for two more intervals after its
+// read).  For R = 8 a wavefront holds 2*kRowCkpt rows, and the one in its
+// middle is the bottom row of lane kRowCkpt/R - 1, which that lane stores in
+// every step (rowck_mid_store).  Checkpoint stores are non-temporal: the
 // backward reads a fraction of them, later, and they should not leave the
 // caches full of dirty lines.
 template <int T, int KS, int SH>
@@ -271,6 +274,22 @@ __device__ __forceinline__ void rowck_copy(const FwdParams& p, const PassGeom& G
 // column with selects (stored at the interval's end), or store it in the
 // step that reaches it (checkpoints closer than one barrier interval).
 enum CkptMode { kCkNone = 0, kCkSelect = 1, kCkEachStep = 2 };
+
+// The row checkpoint inside a wavefront of R = 8 rows per lane: lane
+// kRowCkpt/R - 1 stores its bottom row over the tile of step g.
+template <int R, int T>
+__device__ __forceinline__ void rowck_mid_store(const FwdParams& p, const PassGeom& G,
+                                                const float (&bot)[T], int g) {
+  static_assert(R * kWave == 2 * kRowCkpt, "one row checkpoint inside a wavefront");
+  if (G.rowck_mid != nullptr && G.lane == kRowCkpt / R - 1) {
+    const int tau = g - G.my_delay;
+    if (tau >= 0 && tau < G.ntiles) {
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        if (tau * T + t < p.ref_len) __builtin_nontemporal_store(bot[t], &G.rowck_mid[tau * T + t]);
+    }
+  }
+}
 
 // One step: the R x T block of this lane's current tile.  OUTK >= 0 marks
 // the wavefront holding the row to store and that row's register index.
@@ -388,6 +407,7 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
 #pragma unroll
     for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
   }
+  if constexpr (CKM != kCkNone && R * kWave > kRowCkpt) rowck_mid_store<R, T>(p, G, L.bot, g);
 }
 
 // LDS inputs of step g, read one step ahead: this lane's reference tile and,
@@ -551,6 +571,12 @@ __device__ __forceinline__ void fwd_one_pass(const FwdParams& p, int b, PassGeom
   G.rowck = CKPT && p.rowck != nullptr && bnd > 0 && bnd % kRowCkpt == 0 && bnd < G.n
                 ? p.rowck + (G.qoff / kRowCkpt + bnd / kRowCkpt - 1) * (int64_t)p.ref_len
                 : nullptr;
+  // (RR = 8: the row kRowCkpt below that one lies inside this wave)
+  const int mid = bnd + kRowCkpt;
+  G.rowck_mid = CKPT && RR * kWave > kRowCkpt && p.rowck != nullptr && mid % kRowCkpt == 0 &&
+                        mid < G.n
+                    ? p.rowck + (G.qoff / kRowCkpt + mid / kRowCkpt - 1) * (int64_t)p.ref_len
+                    : nullptr;
   LaneState<RR, T, V> L;
 #pragma unroll
   for (int k = 0; k < RR; ++k) {

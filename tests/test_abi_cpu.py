@@ -140,15 +140,17 @@ def test_workspace_sizes(L):
     assert all_ >= P.sdtw_align_workspace_bytes(lens, 50000, 1024)
     assert P.sdtw_workspace_bytes(lens, 50000, 0, 0) == P.sdtw_forward_workspace_bytes(lens, 50000)
     assert P.sdtw_workspace_bytes(lens, 50000, ck, 24) == 0
-    # checkpoint columns: ceil(M/K) - 1 per query row; then floor(sum/512)
-    # rows of M values (row checkpoints every 512 rows)
+    # checkpoint columns: ceil(M/K) - 1 per query row; then floor(sum/256)
+    # rows of M values (row checkpoints every 256 rows)
     rows = int(lens.sum()) // P.SDTW_ROW_CKPT_EVERY
     assert P.sdtw_checkpoint_floats(lens, 1000, 256) == lens.sum() * 3 + rows * 1000
     assert P.sdtw_checkpoint_floats(lens, 1024, 256) == lens.sum() * 3 + rows * 1024
     assert P.sdtw_checkpoint_floats(lens, 1025, 256) == lens.sum() * 4 + rows * 1025
     assert P.sdtw_checkpoint_floats(lens, 256, 256) == 0
+    # (the row region is sized by the batch total: two rows here, one for
+    # D(256, .) of the 511-row query and one that no query owns)
     short = np.array([511, 1], np.int32)
-    assert P.sdtw_checkpoint_floats(short, 1000, 256) == 512 * 3 + 1000
+    assert P.sdtw_checkpoint_floats(short, 1000, 256) == 512 * 3 + 2 * 1000
 
 
 def _bwd(L, lens, ref_len=100, kind=0, every=64, ckpt=FAKE, ws_bytes=1 << 40, **ptrs):

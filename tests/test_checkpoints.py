@@ -2,9 +2,10 @@
 (every K reference columns) equal the oracle's DP columns bit for bit, for
 every compiled variant, several K (both ways the kernel finds the checkpoint
 column, and stores per step or per barrier interval) and queries that need
-several row passes; so do the row checkpoints (every 512 rows), which reach
-the store through wavefront handoffs or, between row passes, through the row
-buffer."""
+several row passes; so do the row checkpoints (every 256 rows), which reach
+the store through wavefront handoffs, between row passes through the row
+buffer, or (8 rows per lane) from the lane holding the middle row of a
+wavefront."""
 import numpy as np
 import pytest
 import torch
@@ -41,7 +42,7 @@ def test_checkpoint_columns_all_variants(kind):
     for K in (16, 64, 256, 1024):
         want, nck = _expected(rows, K)
         size = P.sdtw_checkpoint_floats(w.lens, REF_LEN, K)
-        assert size == want.size + (sum(LENS) // 512) * REF_LEN
+        assert size == want.size + (sum(LENS) // P.SDTW_ROW_CKPT_EVERY) * REF_LEN
         for v in range(P.sdtw_variant_count()):
             print(f"kind {kind} K {K} variant {v} {P.sdtw_variant_info(v)}", flush=True)
             ckpt = torch.full((size,), float("nan"), dtype=torch.float32, device=q.device)
@@ -53,13 +54,13 @@ def test_checkpoint_columns_all_variants(kind):
                                    f"first at {bad[:4]}: {got[bad[:4]]} vs {want[bad[:4]]}")
 
 
-ROW_LENS = [1100, 300, 2050, 513, 512, 1536, 1537]
+ROW_LENS = [1100, 300, 2050, 513, 512, 1536, 1537, 256, 257, 769, 255]
 ROW_REF = 3000
 
 
 def _row_expected(w, kind):
-    """{region row: D(512k, 1..M)} for every row checkpoint of the batch."""
-    step = 512
+    """{region row: D(256k, 1..M)} for every row checkpoint of the batch."""
+    step = 256
     off, rows = 0, {}
     for b in range(w.batch):
         n = w.lens[b]
@@ -73,7 +74,7 @@ def _row_expected(w, kind):
 @pytest.mark.parametrize("kind", [0, 1])
 def test_row_checkpoints_all_variants(kind):
     import paper_2403_06931_amd as P
-    assert P.SDTW_ROW_CKPT_EVERY == 512
+    assert P.SDTW_ROW_CKPT_EVERY == 256
     w = workloads.make_random(len(ROW_LENS), ROW_LENS, ROW_REF, seed=91 + kind)
     rows = _row_expected(w, kind)
     total = sum(ROW_LENS)
@@ -81,7 +82,7 @@ def test_row_checkpoints_all_variants(kind):
     for K in (64, 1024):
         nck = (ROW_REF + K - 1) // K - 1
         size = P.sdtw_checkpoint_floats(w.lens, ROW_REF, K)
-        assert size == total * nck + (total // 512) * ROW_REF
+        assert size == total * nck + (total // 256) * ROW_REF
         base = total * nck
         cases = [(v, P.SDTW_F_CHECKPOINT) for v in range(P.sdtw_variant_count())]
         cases += [(v, P.SDTW_F_CHECKPOINT | P.SDTW_F_PERSISTENT) for v in (0, 6, 12)]
