@@ -173,6 +173,11 @@ def sample_sclk(run, launches, torch):
     # samples taken while the GPU was busy: a profiler that serialises the
     # launches leaves the GPU idle (at its idle clock) between them
     busy = [v for v in vals if v >= 0.5 * vals[-1]]
+    if busy[-1] < 1000:
+        # every sample at an idle-level clock (below 1 GHz): the launches did
+        # not keep the GPU busy while sampling (a profiler serialises them),
+        # so there is no loaded clock to report
+        return None
     return {"ghz": busy[len(busy) // 2] / 1000.0, "samples": len(vals), "busy_samples": len(busy),
             "min_ghz": vals[0] / 1000.0, "max_ghz": vals[-1] / 1000.0}
 
