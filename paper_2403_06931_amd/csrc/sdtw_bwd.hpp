@@ -525,30 +525,35 @@ __host__ __device__ constexpr size_t bwd_grad_lds_bytes(int max_rows) {
 }
 
 // grad_q[i] of one row: the run of columns hi, hi-1, .., lo (src[j - off]
-// is the reference value of column j), in batches of B loaded one batch
-// ahead.
+// is the reference value of column j), added in that order.  Whole batches
+// of B columns are read at fixed offsets from one pointer, the next batch
+// while the current one is added (at the last whole batch the "next" read
+// repeats the current one, which stays in bounds); the fewer than B columns
+// left are added one by one.
 template <int KIND, int B>
 __device__ __forceinline__ float row_sum(const float* __restrict__ src, int off, float qi,
                                          float gcost, int lo, int jj) {
   float acc = 0.0f;
+  const float* s = src + (jj - off);            // column jj
+  const int full = (jj - lo + 1) / B;
   float rv[B], nx[B];
+  if (full > 0) {
 #pragma unroll
-  for (int u = 0; u < B; ++u) nx[u] = src[(jj - u >= lo ? jj - u : lo) - off];
-  while (jj - (B - 1) >= lo) {
+    for (int u = 0; u < B; ++u) nx[u] = s[-u];
+  }
+  for (int k = 0; k < full; ++k) {
 #pragma unroll
     for (int u = 0; u < B; ++u) rv[u] = nx[u];
-    const int jn = jj - B;
+    s -= B;
+    const float* ld = k + 1 < full ? s : s + B;
 #pragma unroll
-    for (int u = 0; u < B; ++u) nx[u] = src[(jn - u >= lo ? jn - u : lo) - off];
+    for (int u = 0; u < B; ++u) nx[u] = ld[-u];
 #pragma unroll
     for (int u = 0; u < B; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
-    jj = jn;
   }
-  // the last, partial batch: columns jj .. lo (fewer than B)
-  const int rem = jj - lo;
-#pragma unroll
-  for (int u = 0; u < B - 1; ++u)
-    if (u <= rem) acc = acc + gcost * dcost_dq<KIND>(qi, nx[u]);
+  // the columns left: s[0], s[-1], .. down to column lo
+  const int rem = (jj - lo + 1) - full * B;
+  for (int u = 0; u < rem; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, s[-u]);
   return acc;
 }
 
@@ -632,7 +637,24 @@ __global__ __launch_bounds__(kGradThreads) void sdtw_bwd_grad_kernel(const BwdPa
       for (int u = 0; u < kGradBatch; ++u) {
         const int jj = jb + u;
         if (jj < j1) {
-          while (top < n && rhi[top] < jj) qtop = q[(++top) - 1];
+          // top row of column jj: the first row whose last column is >= jj
+          // (last columns never decrease with the row), searched from the
+          // previous column's top row by doubling steps, then bisection
+          // (a steep stretch of the path moves it by many rows at once)
+          if (top < n && rhi[top] < jj) {
+            int a = top + 1, z = top + 1, step = 1;
+            while (z < n && rhi[z] < jj) {
+              a = z + 1;
+              z = z + step < n ? z + step : n;
+              step <<= 1;
+            }
+            while (a < z) {
+              const int mid = (a + z) >> 1;
+              if (rhi[mid] >= jj) z = mid; else a = mid + 1;
+            }
+            top = a;
+            qtop = q[top - 1];
+          }
           // bottom row of column jj: the last row whose first column is <= jj
           // (first columns never decrease with the row; a binary search for
           // the rare vertical runs)
