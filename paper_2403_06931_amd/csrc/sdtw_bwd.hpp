@@ -527,29 +527,41 @@ __host__ __device__ constexpr size_t bwd_grad_lds_bytes(int max_rows) {
 // grad_q[i] of one row: the run of columns hi, hi-1, .., lo (src[j - off]
 // is the reference value of column j), added in that order.  Whole batches
 // of B columns are read at fixed offsets from one pointer, the next batch
-// while the current one is added (at the last whole batch the "next" read
-// repeats the current one, which stays in bounds); the fewer than B columns
-// left are added one by one.
+// while the current one is added, into two register sets used in turn (at
+// the last whole batch the "next" read repeats the current one, which stays
+// in bounds); the fewer than B columns left are added one by one.
+template <int KIND, int B>
+__device__ __forceinline__ void row_batch(float& acc, float qi, float gcost, const float (&v)[B]) {
+#pragma unroll
+  for (int u = 0; u < B; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, v[u]);
+}
+
+template <int B>
+__device__ __forceinline__ void row_load(float (&v)[B], const float* s) {
+#pragma unroll
+  for (int u = 0; u < B; ++u) v[u] = s[-u];
+}
+
 template <int KIND, int B>
 __device__ __forceinline__ float row_sum(const float* __restrict__ src, int off, float qi,
                                          float gcost, int lo, int jj) {
   float acc = 0.0f;
   const float* s = src + (jj - off);            // column jj
   const int full = (jj - lo + 1) / B;
-  float rv[B], nx[B];
-  if (full > 0) {
-#pragma unroll
-    for (int u = 0; u < B; ++u) nx[u] = s[-u];
-  }
-  for (int k = 0; k < full; ++k) {
-#pragma unroll
-    for (int u = 0; u < B; ++u) rv[u] = nx[u];
+  float va[B], vb[B];
+  if (full > 0) row_load<B>(va, s);
+  int k = 0;
+  for (; k + 1 < full; k += 2) {                // batches k (in va) and k+1
+    row_load<B>(vb, s - B);
+    row_batch<KIND, B>(acc, qi, gcost, va);
     s -= B;
-    const float* ld = k + 1 < full ? s : s + B;
-#pragma unroll
-    for (int u = 0; u < B; ++u) nx[u] = ld[-u];
-#pragma unroll
-    for (int u = 0; u < B; ++u) acc = acc + gcost * dcost_dq<KIND>(qi, rv[u]);
+    row_load<B>(va, k + 2 < full ? s - B : s);
+    row_batch<KIND, B>(acc, qi, gcost, vb);
+    s -= B;
+  }
+  if (k < full) {                               // the last whole batch, in va
+    row_batch<KIND, B>(acc, qi, gcost, va);
+    s -= B;
   }
   // the columns left: s[0], s[-1], .. down to column lo
   const int rem = (jj - lo + 1) - full * B;
