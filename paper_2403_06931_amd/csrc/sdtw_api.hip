@@ -269,10 +269,11 @@ constexpr size_t kBwdCodeBudget = size_t(2) << 30;
 // walk ends) are bound by issue slots, where bands would only add pipeline
 // fill and more wavefronts beside the walkers: whole blocks there.
 constexpr int kFirstBandedKernel = 1;
-// Band height, a multiple of the row-checkpoint spacing.  (Bands of 512
-// rows in the first banded kernel and 256 after it measured 1.58 ms per
-// backward on workload 4, 512 throughout 1.61-1.62 ms, 256 throughout
-// 1.52 ms: the shorter latency outweighs the extra pipeline fill.)
+// Band height, a multiple of the row-checkpoint spacing.  (On 256 x 1,000
+// vs 50,000, bands of 512 rows in the first banded kernel and 256 after it
+// measured 1.58 ms per backward, 512 throughout 1.61-1.62 ms, 256
+// throughout 1.52 ms: the shorter latency outweighs the extra pipeline
+// fill.)
 constexpr int kBandRows = 256;
 static_assert(kBandRows % sdtw::kRowCkpt == 0, "bands start on row checkpoints");
 
