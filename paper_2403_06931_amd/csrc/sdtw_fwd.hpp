@@ -97,7 +97,13 @@ struct FwdShape {
   static constexpr int CHUNK = KS * T;                        // floats staged per interval
   static constexpr int SLOTS = XL ? W * kWave * T : 0;        // lane -> lane slots
   static constexpr int OUTBUF = KS * T;                       // row N over one interval
+  // R = 8: the row checkpoint in the middle of each wavefront, one ring per
+  // wavefront like the handoff rings
+  // (checkpointing kernels only, after the other buffers)
+  static constexpr int MIDRING = R * kWave > kRowCkpt ? W * SH * T : 0;
   static constexpr int LDS_FLOATS = SR * T + W * SH * T + SLOTS + OUTBUF;
+  template <bool CKPT>
+  static constexpr int lds_floats() { return LDS_FLOATS + (CKPT ? MIDRING : 0); }
 };
 
 // Stage the reference tiles [tile0, tile0 + KS) and the wave-0 top boundary
@@ -213,6 +219,7 @@ struct PassGeom {
   int64_t qoff;
   float* row;                                // row-buffer slot of the query
   float* s_out;                              // LDS: row N over one interval
+  float* s_mid;                              // LDS: mid-wavefront checkpoint rings
 };
 
 // Store the lane's rows at checkpoint column ck_k from `v` and move on to
@@ -247,8 +254,8 @@ __device__ __forceinline__ void ckpt_flush(const FwdParams& p, LaneState<R, T>& 
 // copies the tiles it read in barrier interval `it` to global memory at the
 // interval's end (a tile stays in the ring for two more intervals after its
 // read).  For R = 8 a wavefront holds 2*kRowCkpt rows, and the one in its
-// middle is the bottom row of lane kRowCkpt/R - 1, which that lane stores in
-// every step (rowck_mid_store).  Checkpoint stores are non-temporal: the
+// middle is the bottom row of lane kRowCkpt/R - 1, which goes through a ring
+// of its own (rowck_mid_put, rowck_mid_copy).  Checkpoint stores are non-temporal: the
 // backward reads a fraction of them, later, and they should not leave the
 // caches full of dirty lines.
 template <int T, int KS, int SH>
@@ -276,17 +283,33 @@ __device__ __forceinline__ void rowck_copy(const FwdParams& p, const PassGeom& G
 enum CkptMode { kCkNone = 0, kCkSelect = 1, kCkEachStep = 2 };
 
 // The row checkpoint inside a wavefront of R = 8 rows per lane: lane
-// kRowCkpt/R - 1 stores its bottom row over the tile of step g.
-template <int R, int T>
-__device__ __forceinline__ void rowck_mid_store(const FwdParams& p, const PassGeom& G,
-                                                const float (&bot)[T], int g) {
+// kRowCkpt/R - 1 writes its bottom row over the tile of step g into its
+// wavefront's ring, and at the end of each barrier interval the wavefront
+// copies the tiles of that interval to global memory (rowck_mid_copy), as
+// for the rows handed over at wavefront boundaries.
+template <int R, int T, int SH>
+__device__ __forceinline__ void rowck_mid_put(const PassGeom& G, const float (&bot)[T], int g) {
   static_assert(R * kWave == 2 * kRowCkpt, "one row checkpoint inside a wavefront");
   if (G.rowck_mid != nullptr && G.lane == kRowCkpt / R - 1) {
-    const int tau = g - G.my_delay;
-    if (tau >= 0 && tau < G.ntiles) {
+    float* dst = G.s_mid + (G.wave * SH + ((g - G.my_delay) & (SH - 1))) * T;
 #pragma unroll
-      for (int t = 0; t < T; ++t)
-        if (tau * T + t < p.ref_len) __builtin_nontemporal_store(bot[t], &G.rowck_mid[tau * T + t]);
+    for (int t = 0; t < T; ++t) dst[t] = bot[t];
+  }
+}
+
+template <int R, int T, int KS, int SH>
+__device__ __forceinline__ void rowck_mid_copy(const FwdParams& p, const PassGeom& G, int it) {
+  const float* ring = G.s_mid + G.wave * SH * T;
+  const int tau0 = it * KS - (G.lane0_delay + kRowCkpt / R - 1);
+#pragma unroll
+  for (int e0 = 0; e0 < KS * T; e0 += kWave) {
+    const int e = e0 + G.lane;
+    if (e < KS * T) {
+      const int tau = tau0 + e / T;
+      const int col = tau * T + (e & (T - 1));
+      if (tau >= 0 && tau < G.ntiles && col < p.ref_len)
+        __builtin_nontemporal_store(ring[(tau & (SH - 1)) * T + (e & (T - 1))],
+                                    &G.rowck_mid[col]);
     }
   }
 }
@@ -407,7 +430,8 @@ __device__ __forceinline__ void fwd_step(const FwdParams& p, LaneState<R, T, V>&
 #pragma unroll
     for (int k = 0; k < R; ++k) L.ckv[k] = hit ? L.dl[k] : L.ckv[k];
   }
-  if constexpr (CKM != kCkNone && R * kWave > kRowCkpt) rowck_mid_store<R, T>(p, G, L.bot, g);
+  if constexpr (CKM != kCkNone && R * kWave > kRowCkpt)
+    rowck_mid_put<R, T, FwdShape<R, T, W, KS, XL>::SH>(G, L.bot, g);
 }
 
 // LDS inputs of step g, read one step ahead: this lane's reference tile and,
@@ -522,6 +546,10 @@ __device__ __forceinline__ void fwd_pass(const FwdParams& p, LaneState<R, T, V>&
       if (G.rowck != nullptr)
         rowck_copy<T, KS, FwdShape<R, T, W, KS, XL>::SH>(p, G, reinterpret_cast<float*>(s_hand),
                                                           it);
+      if constexpr (R * kWave > kRowCkpt) {
+        if (G.rowck_mid != nullptr)
+          rowck_mid_copy<R, T, KS, FwdShape<R, T, W, KS, XL>::SH>(p, G, it);
+      }
     }
     if constexpr (OUTK >= 0) {
       if (G.final_pass) {
@@ -685,6 +713,7 @@ __device__ __forceinline__ void fwd_query(const FwdParams& p, int b, int64_t qof
   G.qoff = qoff;
   G.row = row;
   G.s_out = reinterpret_cast<float*>(s_slot + S0::SLOTS);
+  G.s_mid = G.s_out + S0::OUTBUF;
   using In = typename Val<V>::In;
   const In* __restrict__ q = reinterpret_cast<const In*>(p.queries) + qoff;
   // second query of a binary16 pair (the same one at the end of an odd batch)
@@ -787,7 +816,7 @@ __device__ __forceinline__ int64_t wave_query_offset(const FwdParams& p, int b) 
 template <int R, int T, int W, int KS, int XL, int KIND, bool CKPT>
 __global__ __launch_bounds__(kWave * W) void sdtw_fwd_kernel(const FwdParams p) {
   using S = FwdShape<R, T, W, KS, XL>;
-  __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS];
+  __shared__ __attribute__((aligned(16))) float s_mem[S::template lds_floats<CKPT>()];
   const int b = blockIdx.x;
   const QueryPos qp = query_pos(p, b, S::ROWS);
   float* row = p.rowbuf + (int64_t)qp.slot * p.row_stride;
@@ -829,11 +858,12 @@ __global__ __launch_bounds__(kWave * W * persistent_teams(W)) void sdtw_fwd_pers
     const FwdParams p) {
   using S = FwdShape<R, T, W, KS, XL>;
   constexpr int TEAMS = persistent_teams(W);
-  __shared__ __attribute__((aligned(16))) float s_mem[S::LDS_FLOATS * TEAMS];
+  constexpr int TEAM_FLOATS = S::template lds_floats<CKPT>();
+  __shared__ __attribute__((aligned(16))) float s_mem[TEAM_FLOATS * TEAMS];
   __shared__ int s_item;
   const int team = TEAMS > 1 ? wave_id() : 0;
   float* row = p.rowbuf + ((int64_t)blockIdx.x * TEAMS + team) * p.row_stride;
-  float* mem = s_mem + team * S::LDS_FLOATS;
+  float* mem = s_mem + team * TEAM_FLOATS;
   // The team's wave 0 pops the next item: every lane takes part in the
   // atomic (lane 0 adds 1, the others 0) so there is no lane-dependent
   // branch; with several waves the value is broadcast through LDS.  The
